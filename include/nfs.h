@@ -1,0 +1,168 @@
+/*
+ * nfs.h -- C ABI of the MI355X (gfx950) structure-function library.
+ *
+ * The library computes the structure function of Eq. (1) of Cerchiari,
+ * Croccolo, Cardinaux and Scheffold, "Quasi-real-time analysis of dynamic
+ * near field scattering data using a graphics processing unit":
+ *
+ *   D(q, tau) = < |Delta I_m(q, tau)|^2 >,
+ *
+ * where Delta I_m is the spatial Fourier transform of the difference of two
+ * mean-normalised images taken tau frames apart, the average runs over all
+ * pairs of frames tau apart (ensemble average taken over time, text after
+ * Eq. 1) and the result is averaged azimuthally over rings of |q| (Fig. 1e-f).
+ * As in the processing section of the paper, every image is transformed once
+ * and only differences of transforms are formed (linearity of the Fourier
+ * transform), normalisation divides each transform by its zero-frequency
+ * value, and the per-delay averages are accumulated as the images arrive.
+ *
+ * Conventions (the paper leaves these open):
+ *   - forward transform kernel exp(-2*pi*i*k.x/n), unnormalised, applied to
+ *     the mean-normalised image, so I(0) = n^2; the library sets I(0) = n^2
+ *     exactly in every stored spectrum;
+ *   - bins are half-open rings of width pi/n_bins in q = 2*pi*|k|/n,
+ *     b(k) = isqrt(|k|^2 * n_bins^2) / (n/2); modes with |k| >= n/2 belong to
+ *     no bin;
+ *   - D(b, tau) = sum over modes k of bin b of P_tau(k), divided by C_b, the
+ *     number of full-plane modes in bin b, with
+ *     P_tau(k) = 1/(N - tau) * sum_{t=0}^{N-1-tau} |I_t(k) - I_{t+tau}(k)|^2.
+ *
+ * Memory: the caller allocates one device workspace (nfs_plan_workspace_size)
+ * and every output; the library never allocates or frees device memory.
+ * Streams: every call that touches the device only enqueues work on the
+ * plan's stream and returns; results are valid once that stream has passed
+ * the work. One host thread may use a handle at a time.
+ * Errors: every entry point returns an nfs_status; nothing is thrown across
+ * the ABI. Argument and state errors are detected on the host before any
+ * work is enqueued, and nfs_last_error() then describes them.
+ */
+#ifndef NFS_H
+#define NFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nfs_plan_s* nfs_handle;
+
+typedef enum {
+  NFS_OK = 0,
+  NFS_E_ARG = 1,              /* null pointer or invalid enum value          */
+  NFS_E_SIZE = 2,             /* n not a power of two in [16, 4096]          */
+  NFS_E_LAGS = 3,             /* lags empty, negative, unsorted, duplicated,
+                                 or the largest lag beyond what the pair
+                                 kernel's on-chip history can hold (2400)    */
+  NFS_E_BINS = 4,             /* n_bins outside [1, n/2]                     */
+  NFS_E_WORKSPACE = 5,        /* workspace null, misaligned or too small     */
+  NFS_E_CAPACITY = 6,         /* ring capacity not larger than the max lag   */
+  NFS_E_STATE = 7,            /* handle destroyed or used out of order       */
+  NFS_E_DEGENERATE_FRAME = 8, /* a frame had a non-positive spatial sum      */
+  NFS_E_HIP = 9,              /* a HIP runtime call failed                   */
+  NFS_E_UNSUPPORTED = 10      /* option value not implemented                */
+} nfs_status;
+
+/* Pixel type of the frames passed to nfs_push_frames. */
+enum { NFS_IN_U16 = 0, NFS_IN_F32 = 1 };
+/* Storage type of the resident spectra (only FP32 is implemented). */
+enum { NFS_SPEC_F32 = 0 };
+/* Per-mode pair accumulation (only plain FP32 is implemented). */
+enum { NFS_ACC_PLAIN = 0 };
+
+typedef struct {
+  int32_t n;            /* frame side; frames are n x n, row-major; power of
+                           two in [16, 4096] (the paper processed 32x32 up to
+                           4k x 4k images, processing section)                */
+  int32_t in_dtype;     /* NFS_IN_U16 or NFS_IN_F32                           */
+  int32_t spec_dtype;   /* NFS_SPEC_F32                                       */
+  int32_t accum;        /* NFS_ACC_PLAIN                                      */
+  int32_t n_lags;       /* number of delays, >= 1                             */
+  const int32_t* lags;  /* host array of n_lags delays in frames, strictly
+                           increasing, lags[0] >= 0; copied by nfs_plan. The
+                           paper evaluates all N-1 delays and suggests
+                           log-spaced ones (discussion section)              */
+  int32_t n_bins;       /* number of |q| rings, 1 .. n/2                      */
+  int64_t capacity;     /* spectra kept resident (ring slots); must exceed the
+                           largest lag; 0 = as many as the workspace holds    */
+  const float* window;  /* device [n][n] per-pixel weight multiplied into
+                           every frame before normalisation, or NULL;
+                           borrowed: must stay valid while the plan is used   */
+} nfs_desc;
+
+/* Bytes of device workspace nfs_plan needs for `desc`. Host only; enqueues
+ * nothing. With desc->capacity == 0 the size for a ring of
+ * max(largest lag + 1, 64) spectra is returned. Memory plan made before any
+ * frame is processed, as in the processing section. */
+nfs_status nfs_plan_workspace_size(const nfs_desc* desc, size_t* bytes);
+
+/* Create a plan. `workspace` is a device buffer of `bytes` bytes, 256-byte
+ * aligned, owned by the caller, that must outlive the handle. `stream` is a
+ * hipStream_t (NULL = the default stream) on which all work is enqueued.
+ * Initialises the workspace (enqueued) and returns the handle in *out.
+ * Synchronises `stream` once, to finish the upload of the plan's tables. */
+nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes,
+                    void* stream, nfs_handle* out);
+
+/* Append `count` frames to the sequence: device array [count][n][n] of the
+ * plan's pixel type, borrowed until the stream passes the enqueued work.
+ * Each frame is normalised, transformed once and stored in the ring (the
+ * per-image transforms of the processing section); pair sums are
+ * accumulated whenever the ring would otherwise overwrite a spectrum that a
+ * later pair still needs. Frame indices continue across calls. count == 0 is
+ * a no-op. */
+nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count);
+
+/* Finish the pair sums for every frame pushed so far and write, all on the
+ * device:
+ *   D          double [n_lags][n_bins]: D(b, tau) as defined above; NaN for a
+ *              delay with no pair (N - tau <= 0); exactly 0 for tau = 0;
+ *   bin_counts int64 [n_bins]: C_b, full-plane modes per ring (may be NULL);
+ *   lag_pairs  int64 [n_lags]: max(0, N - tau) (may be NULL);
+ *   status     int32 [1]: NFS_OK, or NFS_E_DEGENERATE_FRAME when some pushed
+ *              frame had a spatial sum <= 0 (sticky until nfs_reset; such a
+ *              frame's spectrum is stored as zero except I(0) = n^2)
+ *              (may be NULL).
+ * May be called again after more pushes; the sums keep growing. */
+nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
+                                  int64_t* lag_pairs, int32_t* status);
+
+/* Forget all frames and sums (enqueued); the plan can be reused. */
+nfs_status nfs_reset(nfs_handle h);
+
+/* Release the host-side plan. The workspace stays the caller's. Returns
+ * NFS_E_STATE when called twice. */
+nfs_status nfs_destroy(nfs_handle h);
+
+/* Static description of a status code. */
+const char* nfs_status_string(nfs_status s);
+
+/* Description of the last error on this handle ("" if none); valid until
+ * the next call on the handle. */
+const char* nfs_last_error(nfs_handle h);
+
+/* Inspection entry points (tests and tools).
+ *
+ * nfs_mode_count: number M of modes stored per spectrum. Only the modes
+ * that can land in a bin are stored: k_x in [0, n/2) and |k| < n/2 (the
+ * half-plane is enough for real images; the k_x = n/2 line and the corners
+ * belong to no bin). Host only.
+ *
+ * nfs_bin_map: device int32 [n][n/2]; entry [r][k_x] is the bin of mode
+ * (k_y, k_x), with r the transform-order row of k_y, or -1 when the mode is
+ * in no bin; computed by the same device code that bins the sums.
+ *
+ * nfs_copy_spectrum: device float [n][n/2][2]: the stored spectrum of
+ * pushed frame `t` (real, imaginary) on the half plane k_x in [0, n/2), 0 at
+ * modes that are not stored. Only frames still in the ring can be copied:
+ * NFS_E_STATE otherwise. */
+nfs_status nfs_mode_count(nfs_handle h, int64_t* modes);
+nfs_status nfs_bin_map(nfs_handle h, int32_t* map);
+nfs_status nfs_copy_spectrum(nfs_handle h, int64_t t, float* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NFS_H */

@@ -154,13 +154,14 @@ def structure_function(frames, lags, n_bins, window=None, return_power=False):
     return out
 
 
-def structure_function_bins(frames, lags, n_bins, bins, window=None):
+def structure_function_bins(frames, lags, n_bins, bins, window=None, workers=1):
     """Steps O1-O6 for a few bins only, for stacks too large to hold in FP64.
 
-    Frames are normalised and transformed one at a time and only the modes
-    of the requested bins are kept. Returns D float64 [L][len(bins)],
-    counts int64 [len(bins)] and pairs int64 [L], equal to the matching
-    columns of structure_function().
+    Frames are normalised and transformed one at a time (by `workers`
+    threads, each doing whole frames) and only the modes of the requested
+    bins are kept. Returns D float64 [L][len(bins)], counts int64
+    [len(bins)] and pairs int64 [L], equal to the matching columns of
+    structure_function().
     """
     N = len(frames)
     n = int(np.asarray(frames[0]).shape[-1])
@@ -169,9 +170,18 @@ def structure_function_bins(frames, lags, n_bins, bins, window=None):
     sel = np.isin(bidx, bins)
     keep = np.empty((N, int(sel.sum())), dtype=np.complex128)
     w = None if window is None else np.asarray(window, dtype=np.float64)
-    for t in range(N):
+
+    def one(t):
         norm, _ = normalise(np.asarray(frames[t])[None], w)
         keep[t] = spectra(norm)[0][sel]
+
+    if workers > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, range(N)))
+    else:
+        for t in range(N):
+            one(t)
     P, pairs = pair_power(keep, lags)
     sub_b = bidx[sel]
     counts_all = bin_counts(bidx, n_bins)

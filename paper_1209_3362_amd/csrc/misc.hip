@@ -1,0 +1,69 @@
+// Small utility kernels: fills (used instead of memset nodes so the work
+// can be captured in a graph), the bin map and spectrum expansion used for
+// inspection.
+#include "nfs_device.hpp"
+#include "nfs_kernels.hpp"
+
+namespace nfs {
+namespace {
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ dst, size_t words, uint32_t value) {
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < words;
+       i += size_t(gridDim.x) * blockDim.x)
+    dst[i] = value;
+}
+
+__global__ void bin_map_kernel(int n, int nb, int32_t* __restrict__ map) {
+  const int h = n / 2;
+  const int64_t total = int64_t(n) * h;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int r = int(i / h), kx = int(i % h);
+    const int ky = r < h ? r : r - n;
+    map[i] = dev::bin_of_dev(n, nb, ky, kx);
+  }
+}
+
+__global__ void expand_kernel(int n, const float2* __restrict__ spec,
+                              const int32_t* __restrict__ row_width,
+                              const int32_t* __restrict__ row_offset, float2* __restrict__ out) {
+  const int h = n / 2;
+  const int64_t total = int64_t(n) * h;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int r = int(i / h), kx = int(i % h);
+    out[i] = kx < row_width[r] ? spec[row_offset[r] + kx] : make_float2(0.f, 0.f);
+  }
+}
+
+unsigned grid_for(int64_t items, int threads) {
+  int64_t g = (items + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return unsigned(g);
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(void* dst, size_t words, uint32_t value, hipStream_t s) {
+  if (words == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(int64_t(words), 256)), dim3(256), 0, s,
+                     static_cast<uint32_t*>(dst), words, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_map(int n, int n_bins, int32_t* map, hipStream_t s) {
+  hipLaunchKernelGGL(bin_map_kernel, dim3(grid_for(int64_t(n) * (n / 2), 256)), dim3(256), 0, s,
+                     n, n_bins, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_spectrum(int n, const float2* ring, int64_t slot, int64_t mode_stride,
+                                  const int32_t* row_width, const int32_t* row_offset,
+                                  float2* out, hipStream_t s) {
+  hipLaunchKernelGGL(expand_kernel, dim3(grid_for(int64_t(n) * (n / 2), 256)), dim3(256), 0, s,
+                     n, ring + slot * mode_stride, row_width, row_offset, out);
+  return hipGetLastError();
+}
+
+}  // namespace nfs

@@ -1,0 +1,274 @@
+// C ABI of the structure-function library: plan, push, finish, inspect.
+//
+// A plan carves one caller-owned device workspace (memory planned before
+// the run, as in the processing section of the paper) into a ring of
+// resident spectra, the row-pass intermediate of one batch of frames, the
+// per-lag sums and small tables. Frames are transformed in batches as they
+// are pushed; pair sums are accumulated over the window of frames not yet
+// paired whenever the ring would otherwise evict a spectrum that a pending
+// pair needs, and at the end.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "nfs.h"
+#include "nfs_host.hpp"
+#include "nfs_kernels.hpp"
+
+struct nfs_plan_s {
+  nfs::Layout L;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  const float* window = nullptr;
+  float2* ring = nullptr;
+  float2* inter = nullptr;
+  double* rowsum = nullptr;
+  float* acc = nullptr;
+  int32_t* status = nullptr;
+  float2* tw = nullptr;
+  int32_t* width = nullptr;
+  int32_t* offset = nullptr;
+  int32_t* lags = nullptr;
+  int64_t t_pushed = 0;  // frames pushed
+  int64_t t_done = 0;    // frames whose pairs (as the later frame) are summed
+  std::string err;
+};
+
+namespace {
+
+std::mutex g_mu;
+std::set<nfs_plan_s*>& live() {
+  static std::set<nfs_plan_s*> s;
+  return s;
+}
+
+bool is_live(nfs_plan_s* h) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  return live().count(h) != 0;
+}
+
+nfs_status fail(nfs_plan_s* h, nfs_status s, const std::string& msg) {
+  if (h) h->err = msg;
+  return s;
+}
+
+nfs_status hip_fail(nfs_plan_s* h, hipError_t e, const char* where) {
+  return fail(h, NFS_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Sum pairs whose later frame is in [t_done, t_pushed).
+nfs_status flush_pairs(nfs_plan_s* h) {
+  if (h->t_done >= h->t_pushed) return NFS_OK;
+  const nfs::Layout& L = h->L;
+  for (const nfs::LagGroup& g : L.groups) {
+    hipError_t e = nfs::launch_pairs(h->ring, L.modes, L.mode_stride, L.capacity, h->t_done,
+                                     h->t_pushed, h->lags + g.first, g.count, g.max_lag,
+                                     h->acc + int64_t(g.first) * L.mode_stride, g.modes, g.hist,
+                                     g.waves, g.per_wave, g.lds, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "pair kernel launch");
+  }
+  h->t_done = h->t_pushed;
+  return NFS_OK;
+}
+
+nfs_status clear_sums(nfs_plan_s* h) {
+  const nfs::Layout& L = h->L;
+  hipError_t e = nfs::launch_fill_u32(h->acc, size_t(L.n_lags) * L.mode_stride, 0u, h->stream);
+  if (e == hipSuccess) e = nfs::launch_fill_u32(h->status, 1, 0u, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "fill kernel launch");
+  h->t_pushed = 0;
+  h->t_done = 0;
+  return NFS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nfs_status_string(nfs_status s) {
+  switch (s) {
+    case NFS_OK: return "ok";
+    case NFS_E_ARG: return "invalid argument";
+    case NFS_E_SIZE: return "frame size must be a power of two in [16, 4096]";
+    case NFS_E_LAGS: return "invalid lag list";
+    case NFS_E_BINS: return "n_bins must be in [1, n/2]";
+    case NFS_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case NFS_E_CAPACITY: return "ring capacity must exceed the largest lag";
+    case NFS_E_STATE: return "invalid handle or call order";
+    case NFS_E_DEGENERATE_FRAME: return "a frame had a non-positive spatial sum";
+    case NFS_E_HIP: return "HIP runtime error";
+    case NFS_E_UNSUPPORTED: return "option not implemented";
+  }
+  return "unknown status";
+}
+
+nfs_status nfs_plan_workspace_size(const nfs_desc* desc, size_t* bytes) {
+  if (!bytes) return NFS_E_ARG;
+  nfs::Layout L;
+  std::string err;
+  nfs_status st = nfs::make_layout(desc, 0, &L, &err);
+  if (st != NFS_OK) return st;
+  *bytes = L.total;
+  return NFS_OK;
+}
+
+nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* stream,
+                    nfs_handle* out) {
+  if (!out) return NFS_E_ARG;
+  *out = nullptr;
+  nfs_plan_s* h = new (std::nothrow) nfs_plan_s();
+  if (!h) return NFS_E_ARG;
+  std::string err;
+  nfs_status st = nfs::make_layout(desc, bytes, &h->L, &err);
+  if (st == NFS_OK && (!workspace || (reinterpret_cast<uintptr_t>(workspace) % nfs::kAlign)))
+    st = NFS_E_WORKSPACE;
+  if (st == NFS_OK && bytes < h->L.total) st = NFS_E_WORKSPACE;
+  if (st != NFS_OK) {
+    delete h;
+    return st;
+  }
+  const nfs::Layout& L = h->L;
+  h->stream = static_cast<hipStream_t>(stream);
+  h->ws = static_cast<char*>(workspace);
+  h->window = desc->window;
+  h->ring = reinterpret_cast<float2*>(h->ws + L.off_ring);
+  h->inter = reinterpret_cast<float2*>(h->ws + L.off_inter);
+  h->rowsum = reinterpret_cast<double*>(h->ws + L.off_rowsum);
+  h->acc = reinterpret_cast<float*>(h->ws + L.off_acc);
+  h->status = reinterpret_cast<int32_t*>(h->ws + L.off_status);
+  h->tw = reinterpret_cast<float2*>(h->ws + L.off_tw);
+  h->width = reinterpret_cast<int32_t*>(h->ws + L.off_width);
+  h->offset = reinterpret_cast<int32_t*>(h->ws + L.off_offset);
+  h->lags = reinterpret_cast<int32_t*>(h->ws + L.off_lags);
+
+  const std::vector<float> tw = nfs::twiddle_table(L.n);
+  hipError_t e = hipMemcpyAsync(h->tw, tw.data(), tw.size() * sizeof(float),
+                                hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->width, L.row_width.data(), L.row_width.size() * 4,
+                       hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->offset, L.row_offset.data(), L.row_offset.size() * 4,
+                       hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->lags, L.lags.data(), L.lags.size() * 4, hipMemcpyHostToDevice,
+                       h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return NFS_E_HIP;
+  }
+  st = clear_sums(h);
+  if (st != NFS_OK) {
+    delete h;
+    return st;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    live().insert(h);
+  }
+  *out = h;
+  return NFS_OK;
+}
+
+nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count) {
+  if (!is_live(h)) return NFS_E_STATE;
+  if (count < 0) return fail(h, NFS_E_ARG, "count must be >= 0");
+  if (count == 0) return NFS_OK;
+  if (!frames) return fail(h, NFS_E_ARG, "frames is NULL");
+  const nfs::Layout& L = h->L;
+  const size_t px = L.in_dtype == NFS_IN_U16 ? 2 : 4;
+  const size_t frame_bytes = size_t(L.n) * L.n * px;
+  const int64_t room = L.capacity - L.max_lag;  // >= 1 by construction
+  int64_t i = 0;
+  while (i < count) {
+    int64_t b = count - i;
+    if (b > L.batch) b = L.batch;
+    if (b > room) b = room;
+    // Pushing frames [t_pushed, t_pushed + b) evicts frames up to
+    // t_pushed + b - 1 - capacity; pending pairs need frames from
+    // t_done - max_lag on.
+    if (h->t_pushed + b - L.capacity > h->t_done - L.max_lag) {
+      nfs_status st = flush_pairs(h);
+      if (st != NFS_OK) return st;
+    }
+    const char* src = static_cast<const char*>(frames) + size_t(i) * frame_bytes;
+    hipError_t e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->window, int(b), h->inter,
+                                        h->rowsum, h->tw, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
+    e = nfs::launch_col_pass(L.n, h->inter, h->rowsum, int(b), h->t_pushed, L.capacity,
+                             L.mode_stride, h->width, h->offset, h->tw, h->ring, h->status,
+                             h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
+    h->t_pushed += b;
+    i += b;
+  }
+  return NFS_OK;
+}
+
+nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
+                                  int64_t* lag_pairs, int32_t* status) {
+  if (!is_live(h)) return NFS_E_STATE;
+  if (!D) return fail(h, NFS_E_ARG, "D is NULL");
+  nfs_status st = flush_pairs(h);
+  if (st != NFS_OK) return st;
+  const nfs::Layout& L = h->L;
+  hipError_t e = nfs::launch_bins(L.n, L.n_bins, h->acc, L.mode_stride, h->offset, h->lags,
+                                  L.n_lags, h->t_pushed, h->status, D, bin_counts, lag_pairs,
+                                  status, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "bin kernel launch");
+  return NFS_OK;
+}
+
+nfs_status nfs_reset(nfs_handle h) {
+  if (!is_live(h)) return NFS_E_STATE;
+  return clear_sums(h);
+}
+
+nfs_status nfs_destroy(nfs_handle h) {
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!live().erase(h)) return NFS_E_STATE;
+  }
+  delete h;
+  return NFS_OK;
+}
+
+const char* nfs_last_error(nfs_handle h) {
+  if (!is_live(h)) return "invalid handle";
+  return h->err.c_str();
+}
+
+nfs_status nfs_mode_count(nfs_handle h, int64_t* modes) {
+  if (!is_live(h)) return NFS_E_STATE;
+  if (!modes) return fail(h, NFS_E_ARG, "modes is NULL");
+  *modes = h->L.modes;
+  return NFS_OK;
+}
+
+nfs_status nfs_bin_map(nfs_handle h, int32_t* map) {
+  if (!is_live(h)) return NFS_E_STATE;
+  if (!map) return fail(h, NFS_E_ARG, "map is NULL");
+  hipError_t e = nfs::launch_bin_map(h->L.n, h->L.n_bins, map, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "bin map launch");
+  return NFS_OK;
+}
+
+nfs_status nfs_copy_spectrum(nfs_handle h, int64_t t, float* out) {
+  if (!is_live(h)) return NFS_E_STATE;
+  if (!out) return fail(h, NFS_E_ARG, "out is NULL");
+  if (t < 0 || t >= h->t_pushed || t < h->t_pushed - h->L.capacity)
+    return fail(h, NFS_E_STATE, "frame is not in the ring");
+  hipError_t e = nfs::launch_expand_spectrum(h->L.n, h->ring, t % h->L.capacity,
+                                             h->L.mode_stride, h->width, h->offset,
+                                             reinterpret_cast<float2*>(out), h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "expand launch");
+  return NFS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,206 @@
+// Host-only planning logic; see nfs_host.hpp.
+#include "nfs_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+namespace nfs {
+
+uint64_t isqrt_u64(uint64_t v) {
+  uint64_t s = static_cast<uint64_t>(std::sqrt(static_cast<double>(v)));
+  while (s > 0 && s * s > v) --s;
+  while ((s + 1) * (s + 1) <= v) ++s;
+  return s;
+}
+
+int64_t ceil_sqrt_i64(int64_t v) {
+  if (v <= 0) return 0;
+  int64_t s = static_cast<int64_t>(isqrt_u64(static_cast<uint64_t>(v)));
+  return s * s == v ? s : s + 1;
+}
+
+int bin_of(int n, int nb, int ky, int kx) {
+  const uint64_t r2 = uint64_t(int64_t(kx) * kx + int64_t(ky) * ky);
+  const uint64_t b = isqrt_u64(r2 * uint64_t(nb) * uint64_t(nb)) / uint64_t(n / 2);
+  return b < uint64_t(nb) ? int(b) : -1;
+}
+
+void ring_bounds(int n, int nb, int b, int64_t* lo, int64_t* hi) {
+  // |k|^2 nb^2 >= (b m)^2  <=>  |k|^2 >= ceil((b m)^2 / nb^2), m = n/2.
+  const int64_t m = n / 2, q = int64_t(nb) * nb;
+  const int64_t a = int64_t(b) * m, c = int64_t(b + 1) * m;
+  *lo = (a * a + q - 1) / q;
+  *hi = (c * c + q - 1) / q;
+}
+
+nfs_status validate_desc(const nfs_desc* d, std::string* err) {
+  auto fail = [&](nfs_status s, const char* msg) {
+    if (err) *err = msg;
+    return s;
+  };
+  if (!d) return fail(NFS_E_ARG, "desc is NULL");
+  if (!is_pow2(d->n) || d->n < kMinN || d->n > kMaxN)
+    return fail(NFS_E_SIZE, "n must be a power of two in [16, 4096]");
+  if (d->in_dtype != NFS_IN_U16 && d->in_dtype != NFS_IN_F32)
+    return fail(NFS_E_ARG, "in_dtype must be NFS_IN_U16 or NFS_IN_F32");
+  if (d->spec_dtype != NFS_SPEC_F32)
+    return fail(NFS_E_UNSUPPORTED, "only NFS_SPEC_F32 spectra are implemented");
+  if (d->accum != NFS_ACC_PLAIN)
+    return fail(NFS_E_UNSUPPORTED, "only NFS_ACC_PLAIN accumulation is implemented");
+  if (d->n_lags < 1 || !d->lags) return fail(NFS_E_LAGS, "need at least one lag");
+  for (int i = 0; i < d->n_lags; ++i) {
+    if (d->lags[i] < 0) return fail(NFS_E_LAGS, "lags must be >= 0");
+    if (i && d->lags[i] <= d->lags[i - 1])
+      return fail(NFS_E_LAGS, "lags must be strictly increasing");
+  }
+  if (d->lags[d->n_lags - 1] > kMaxLag)
+    return fail(NFS_E_LAGS, "largest lag exceeds 2400");
+  if (d->n_bins < 1 || d->n_bins > d->n / 2)
+    return fail(NFS_E_BINS, "n_bins must be in [1, n/2]");
+  if (d->capacity < 0) return fail(NFS_E_CAPACITY, "capacity must be >= 0");
+  if (d->capacity > 0 && d->capacity <= d->lags[d->n_lags - 1])
+    return fail(NFS_E_CAPACITY, "capacity must exceed the largest lag");
+  return NFS_OK;
+}
+
+static bool plan_group(const std::vector<int32_t>& lags, int first, int count,
+                       LagGroup* g) {
+  g->first = first;
+  g->count = count;
+  g->max_lag = lags[first + count - 1];
+  g->modes = 0;
+  for (int K : {64, 32, 16, 8}) {
+    const int H = int(align_up(size_t(g->max_lag + 2 * kPairChunk), kPairChunk));
+    const size_t lds = size_t(H + kPairChunk) * K * 8;
+    if (lds <= size_t(kLdsBytes)) {
+      g->modes = K;
+      g->hist = H;
+      g->lds = lds;
+      break;
+    }
+  }
+  if (!g->modes) return false;
+  int best_w = 0, best_waste = std::numeric_limits<int>::max();
+  for (int W = 1; W <= kMaxPairWaves; ++W) {
+    const int per = (count + W - 1) / W;
+    if (per > kMaxLagsPerWave) continue;
+    const int waste = per * W - count;
+    if (waste <= best_waste) {  // ties go to more waves
+      best_waste = waste;
+      best_w = W;
+    }
+  }
+  g->waves = best_w;
+  g->per_wave = (count + best_w - 1) / best_w;
+  return best_w > 0;
+}
+
+nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
+                       std::string* err) {
+  nfs_status st = validate_desc(d, err);
+  if (st != NFS_OK) return st;
+  Layout& o = *L;
+  o = Layout{};
+  o.n = d->n;
+  o.h = d->n / 2;
+  o.n_bins = d->n_bins;
+  o.n_lags = d->n_lags;
+  o.in_dtype = d->in_dtype;
+  o.lags.assign(d->lags, d->lags + d->n_lags);
+  o.max_lag = o.lags.back();
+
+  // Stored modes: k_x in [0, n/2), |k| < n/2; row r has k_y = r (r < n/2)
+  // or r - n, and keeps k_x in [0, width).
+  o.row_width.resize(o.n);
+  o.row_offset.resize(o.n);
+  const int64_t hh = int64_t(o.h) * o.h;
+  int64_t acc = 0;
+  for (int r = 0; r < o.n; ++r) {
+    const int64_t ky = r < o.h ? r : r - o.n;
+    const int64_t rem = hh - 1 - ky * ky;
+    const int w = rem < 0 ? 0 : int(isqrt_u64(uint64_t(rem))) + 1;
+    o.row_width[r] = w;
+    o.row_offset[r] = int32_t(acc);
+    acc += w;
+  }
+  o.modes = acc;
+  o.mode_stride = int64_t(align_up(size_t(acc), 64));
+
+  const int max_group = kMaxLagsPerWave * kMaxPairWaves;
+  for (int first = 0; first < o.n_lags; first += max_group) {
+    LagGroup g;
+    const int count = std::min(max_group, o.n_lags - first);
+    if (!plan_group(o.lags, first, count, &g)) {
+      if (err) *err = "lag group does not fit the pair kernel's history";
+      return NFS_E_LAGS;
+    }
+    o.groups.push_back(g);
+  }
+
+  const size_t inter_frame = size_t(o.n) * o.h * 8;
+  o.batch = int(std::max<size_t>(1, std::min<size_t>(kMaxBatch, kBatchBytes / inter_frame)));
+  // A batch never exceeds what the ring can take beyond the largest lag.
+  if (d->capacity > 0) o.batch = int(std::min<int64_t>(o.batch, d->capacity - o.max_lag));
+
+  // Everything except the ring.
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, kAlign);
+    return at;
+  };
+  o.off_inter = take(size_t(o.batch) * inter_frame);
+  o.off_rowsum = take(size_t(o.batch) * o.n * 8);
+  o.off_acc = take(size_t(o.n_lags) * o.mode_stride * 4);
+  o.off_status = take(kAlign);
+  o.off_tw = take(size_t(o.n) * 8);
+  o.off_width = take(size_t(o.n) * 4);
+  o.off_offset = take(size_t(o.n) * 4);
+  o.off_lags = take(size_t(o.n_lags) * 4);
+  o.off_ring = off;
+  const size_t spec_bytes = size_t(o.mode_stride) * 8;
+
+  if (d->capacity > 0) {
+    o.capacity = d->capacity;
+  } else if (bytes_available > 0) {
+    if (bytes_available <= o.off_ring) {
+      if (err) *err = "workspace too small for any spectrum ring";
+      return NFS_E_WORKSPACE;
+    }
+    o.capacity = int64_t((bytes_available - o.off_ring) / spec_bytes);
+  } else {
+    o.capacity = int64_t(o.max_lag) + 64;
+  }
+  if (o.capacity <= o.max_lag) {
+    if (err) *err = "ring capacity must exceed the largest lag";
+    return NFS_E_CAPACITY;
+  }
+  o.total = align_up(o.off_ring + size_t(o.capacity) * spec_bytes, kAlign);
+  return NFS_OK;
+}
+
+std::vector<float> twiddle_table(int n) {
+  // theta = 2 pi j / n = q * (pi/2) + phi with q the quadrant; cos and sin of
+  // phi in [0, pi/2) in double, rotated by q quarter turns exactly, so the
+  // table is exact at multiples of pi/2 and symmetric between quadrants.
+  std::vector<float> t(size_t(2) * n);
+  const double half_pi = 1.5707963267948966192313216916398;
+  for (int j = 0; j < n; ++j) {
+    const int64_t j4 = int64_t(4) * j;
+    const int q = int(j4 / n);
+    const int64_t rem = j4 - int64_t(q) * n;
+    const double phi = half_pi * double(rem) / double(n);
+    const double c0 = rem ? std::cos(phi) : 1.0;
+    const double s0 = rem ? std::sin(phi) : 0.0;
+    double c = c0, s = s0;
+    if (q == 1) { c = -s0; s = c0; }
+    if (q == 2) { c = -c0; s = -s0; }
+    if (q == 3) { c = s0; s = -c0; }
+    t[2 * j] = float(c);
+    t[2 * j + 1] = float(-s);
+  }
+  return t;
+}
+
+}  // namespace nfs

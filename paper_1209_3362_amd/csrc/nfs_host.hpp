@@ -1,0 +1,88 @@
+// Host-only planning logic of the structure-function library: descriptor
+// validation, the set of stored modes, workspace layout and launch shapes.
+// No HIP dependency, so it also builds with a plain C++ compiler for tests.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "nfs.h"
+
+namespace nfs {
+
+constexpr int kMinN = 16;
+constexpr int kMaxN = 4096;
+constexpr size_t kAlign = 256;
+// Rows of the time series handled per step of the pair kernel.
+constexpr int kPairChunk = 32;
+// Most lags one wave of the pair kernel accumulates at once, and most waves
+// per workgroup; a launch handles at most their product.
+constexpr int kMaxLagsPerWave = 8;
+constexpr int kMaxPairWaves = 16;
+// LDS a workgroup may allocate on gfx950.
+constexpr int kLdsBytes = 160 * 1024;
+// Largest delay the pair kernel's on-chip history supports (K = 8 modes).
+constexpr int kMaxLag = 2400;
+// Target size of the row-transform intermediate of one batch of frames.
+constexpr size_t kBatchBytes = size_t(128) << 20;
+constexpr int kMaxBatch = 1024;
+
+inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Exact integer square root: largest s with s*s <= v.
+uint64_t isqrt_u64(uint64_t v);
+// Smallest s >= 0 with s*s >= v (v >= 0).
+int64_t ceil_sqrt_i64(int64_t v);
+
+// Bin of mode (ky, kx): isqrt(|k|^2 nb^2) / (n/2), or -1 when >= nb.
+int bin_of(int n, int nb, int ky, int kx);
+// Ring b holds the modes with lo <= |k|^2 < hi.
+void ring_bounds(int n, int nb, int b, int64_t* lo, int64_t* hi);
+
+// One group of lags handled by one launch of the pair kernel.
+struct LagGroup {
+  int first = 0;      // index of the group's first lag in the lag list
+  int count = 0;      // lags in the group
+  int max_lag = 0;    // largest lag of the group
+  int modes = 0;      // K: modes per workgroup
+  int hist = 0;       // H: history rows kept in LDS (multiple of kPairChunk)
+  int waves = 0;      // waves per workgroup
+  int per_wave = 0;   // lags per wave (<= kMaxLagsPerWave)
+  size_t lds = 0;     // dynamic LDS bytes
+};
+
+struct Layout {
+  int n = 0, h = 0, n_bins = 0, n_lags = 0;
+  int in_dtype = 0;
+  int64_t modes = 0;       // M: stored modes per spectrum
+  int64_t mode_stride = 0; // M rounded up to 64: ring slot and sum-row pitch
+  int64_t capacity = 0;    // ring slots
+  int batch = 0;           // frames per transform launch
+  int max_lag = 0;
+  std::vector<int32_t> lags;
+  std::vector<int32_t> row_width;   // [n] stored modes of transform-order row r
+  std::vector<int32_t> row_offset;  // [n] first stored index of row r
+  std::vector<LagGroup> groups;
+  // Byte offsets into the workspace.
+  size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_acc = 0;
+  size_t off_status = 0, off_tw = 0, off_width = 0, off_offset = 0;
+  size_t off_lags = 0, total = 0;
+};
+
+// Validates `d`; on failure returns the status and fills `err`.
+nfs_status validate_desc(const nfs_desc* d, std::string* err);
+
+// Builds the layout for `d`. With d->capacity == 0 and bytes_available > 0,
+// the ring takes every whole spectrum that fits; with both 0 the ring has
+// max_lag + 64 slots.
+nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
+                       std::string* err);
+
+// W_n^j = exp(-2 pi i j / n), j = 0..n-1, evaluated in double and rounded
+// once to float; interleaved (re, im).
+std::vector<float> twiddle_table(int n);
+
+}  // namespace nfs

@@ -1,0 +1,62 @@
+// Host-side launchers of the library's HIP kernels. Each returns the HIP
+// status of its launch; argument shapes are checked by the caller.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace nfs {
+
+// Row pass (per image row: real-to-complex transform of n pixels to the
+// n/2 half-plane coefficients k_x = 0..n/2-1) plus exact per-row pixel sums.
+// frames: [nframes][n][n] of u16 (in_dtype 0) or f32 (1); window: [n][n] or
+// null. Writes inter [nframes][n/16][n][8] complex (8-column tiles) and
+// rowsum [nframes][n] double.
+hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const float* window,
+                           int nframes, float2* inter, double* rowsum,
+                           const float2* tw, hipStream_t s);
+
+// Column pass (per column k_x: complex transform over the n rows), scaling
+// by n^2 / (frame sum), I(0) := n^2, and store of the stored modes of each
+// frame f into ring slot (t0 + f) mod capacity. Frames with a non-positive
+// or non-finite sum set bit 0 of *status and are stored with scale 0.
+hipError_t launch_col_pass(int n, const float2* inter, const double* rowsum,
+                           int nframes, int64_t t0, int64_t capacity,
+                           int64_t mode_stride, const int32_t* row_width,
+                           const int32_t* row_offset, const float2* tw,
+                           float2* ring, int32_t* status, hipStream_t s);
+
+// Lag-pair accumulation for target frames [T0, T1) and the lags
+// lags[0..n_lags): acc[l][m] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2 over
+// t in [T0, T1) with t - lag >= 0. Frames [max(0, T0 - max lag), T1) must
+// be in the ring. `modes` per workgroup (64, 32, 16 or 8), `hist` LDS rows,
+// `waves` per workgroup with `per_wave` lags each.
+hipError_t launch_pairs(const float2* ring, int64_t n_modes, int64_t mode_stride,
+                        int64_t capacity, int64_t T0, int64_t T1,
+                        const int32_t* lags, int n_lags, int max_lag, float* acc,
+                        int modes, int hist, int waves, int per_wave, size_t lds,
+                        hipStream_t s);
+
+// Azimuthal binning: D[l][b] = sum_{k in ring b} w(k) acc[l][k] /
+// (C_b * pairs_l) in double, counts[b] = C_b, pairs[l] = max(0, N - lag_l),
+// status_out[0] = *status. pairs_l == 0 gives NaN.
+hipError_t launch_bins(int n, int n_bins, const float* acc, int64_t mode_stride,
+                       const int32_t* row_offset, const int32_t* lags, int n_lags,
+                       int64_t n_frames, const int32_t* status, double* D,
+                       int64_t* counts, int64_t* pairs, int32_t* status_out,
+                       hipStream_t s);
+
+// Fills `words` 32-bit words at dst with `value`.
+hipError_t launch_fill_u32(void* dst, size_t words, uint32_t value, hipStream_t s);
+
+// Writes the bin of every half-plane mode to map [n][n/2].
+hipError_t launch_bin_map(int n, int n_bins, int32_t* map, hipStream_t s);
+
+// Expands ring slot `slot` to out [n][n/2] complex, zeros where not stored.
+hipError_t launch_expand_spectrum(int n, const float2* ring, int64_t slot,
+                                  int64_t mode_stride, const int32_t* row_width,
+                                  const int32_t* row_offset, float2* out,
+                                  hipStream_t s);
+
+}  // namespace nfs

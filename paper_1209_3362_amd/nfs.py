@@ -1,0 +1,211 @@
+"""ctypes binding of libnfs.so (include/nfs.h), same names as the C ABI.
+
+PyTorch supplies device memory and the stream; every step of the analysis
+runs in the library's HIP kernels. There is no fallback: a missing or
+unloadable library raises.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+STATUS = {
+    0: "NFS_OK", 1: "NFS_E_ARG", 2: "NFS_E_SIZE", 3: "NFS_E_LAGS", 4: "NFS_E_BINS",
+    5: "NFS_E_WORKSPACE", 6: "NFS_E_CAPACITY", 7: "NFS_E_STATE",
+    8: "NFS_E_DEGENERATE_FRAME", 9: "NFS_E_HIP", 10: "NFS_E_UNSUPPORTED",
+}
+IN_DTYPES = {"u16": 0, "f32": 1}
+NFS_OK = 0
+NFS_E_DEGENERATE_FRAME = 8
+
+
+class NfsError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+
+
+def status_name(code):
+    return STATUS.get(int(code), str(code))
+
+
+class NfsDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("in_dtype", ctypes.c_int32),
+        ("spec_dtype", ctypes.c_int32),
+        ("accum", ctypes.c_int32),
+        ("n_lags", ctypes.c_int32),
+        ("lags", ctypes.POINTER(ctypes.c_int32)),
+        ("n_bins", ctypes.c_int32),
+        ("capacity", ctypes.c_int64),
+        ("window", ctypes.c_void_p),
+    ]
+
+
+def library_path():
+    return os.environ.get("NFS_LIBRARY", os.path.join(_HERE, "libnfs.so"))
+
+
+_LIB = None
+
+
+def load_library():
+    """Load libnfs.so once and declare the C signatures."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_1209_3362_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sigs = {
+        "nfs_plan_workspace_size": (i32, [ctypes.POINTER(NfsDesc), ctypes.POINTER(sz)]),
+        "nfs_plan": (i32, [ctypes.POINTER(NfsDesc), P, sz, P, ctypes.POINTER(P)]),
+        "nfs_push_frames": (i32, [P, P, i64]),
+        "nfs_structure_function": (i32, [P, P, P, P, P]),
+        "nfs_reset": (i32, [P]),
+        "nfs_destroy": (i32, [P]),
+        "nfs_status_string": (ctypes.c_char_p, [i32]),
+        "nfs_last_error": (ctypes.c_char_p, [P]),
+        "nfs_mode_count": (i32, [P, ctypes.POINTER(i64)]),
+        "nfs_bin_map": (i32, [P, P]),
+        "nfs_copy_spectrum": (i32, [P, i64, P]),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _desc(n, lags, n_bins, in_dtype, capacity, window_ptr):
+    arr = (ctypes.c_int32 * len(lags))(*[int(t) for t in lags])
+    d = NfsDesc(n=int(n), in_dtype=IN_DTYPES[in_dtype], spec_dtype=0, accum=0,
+                n_lags=len(lags), lags=arr, n_bins=int(n_bins),
+                capacity=int(capacity), window=window_ptr)
+    return d, arr
+
+
+def workspace_size(n, lags, n_bins, in_dtype="u16", capacity=0, window=False):
+    """Workspace bytes for a plan (host only; raises NfsError on a bad desc)."""
+    lib = load_library()
+    d, _keep = _desc(n, lags, n_bins, in_dtype, capacity, 1 if window else None)
+    out = ctypes.c_size_t(0)
+    st = lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out))
+    if st != NFS_OK:
+        raise NfsError(st, lib.nfs_status_string(st).decode())
+    return int(out.value)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A structure-function plan on one GPU.
+
+    Plan(n, lags, n_bins, in_dtype="u16"|"f32", capacity=N, window=None)
+    .push(frames)            frames: [count][n][n] uint16/float32 on the device
+    .structure_function()    -> (D float64 [L][n_bins], counts int64 [n_bins],
+                                 pairs int64 [L], status int) on the device
+    """
+
+    def __init__(self, n, lags, n_bins, in_dtype="u16", capacity=0, window=None,
+                 device=None, stream=None):
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the structure-function library needs one")
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.n, self.lags, self.n_bins = int(n), [int(t) for t in lags], int(n_bins)
+        self.in_dtype = in_dtype
+        self.torch_dtype = torch.uint16 if in_dtype == "u16" else torch.float32
+        self.window = None
+        wptr = None
+        if window is not None:
+            w = window.to(device=self.device, dtype=torch.float32).contiguous()
+            if tuple(w.shape) != (self.n, self.n):
+                raise ValueError("window must be [n][n]")
+            self.window = w
+            wptr = w.data_ptr()
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        d, self._lags_keep = _desc(self.n, self.lags, self.n_bins, in_dtype, capacity, wptr)
+        size = ctypes.c_size_t(0)
+        st = self.lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(size))
+        self._check(st, None)
+        self.workspace = torch.empty(int(size.value), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.lib.nfs_plan(ctypes.byref(d), _ptr(self.workspace),
+                                   ctypes.c_size_t(self.workspace.numel()),
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        self._check(st, None)
+        self.handle = h
+        m = ctypes.c_int64(0)
+        self._check(self.lib.nfs_mode_count(self.handle, ctypes.byref(m)))
+        self.modes = int(m.value)
+
+    def _check(self, st, handle=True):
+        if st != NFS_OK:
+            msg = ""
+            if handle and getattr(self, "handle", None):
+                msg = self.lib.nfs_last_error(self.handle).decode()
+            raise NfsError(st, msg or self.lib.nfs_status_string(st).decode())
+
+    def push(self, frames):
+        """Append frames [count][n][n] (device tensor of the plan's pixel type)."""
+        if frames.device != self.device:
+            raise ValueError(f"frames must be on {self.device}")
+        if frames.dtype != self.torch_dtype:
+            raise ValueError(f"frames must be {self.torch_dtype}")
+        if frames.dim() != 3 or tuple(frames.shape[1:]) != (self.n, self.n):
+            raise ValueError("frames must be [count][n][n]")
+        frames = frames.contiguous()
+        self._check(self.lib.nfs_push_frames(self.handle, _ptr(frames),
+                                             ctypes.c_int64(frames.shape[0])))
+        return self
+
+    def structure_function(self, sync=True):
+        L, nb = len(self.lags), self.n_bins
+        D = torch.empty((L, nb), dtype=torch.float64, device=self.device)
+        counts = torch.empty(nb, dtype=torch.int64, device=self.device)
+        pairs = torch.empty(L, dtype=torch.int64, device=self.device)
+        status = torch.empty(1, dtype=torch.int32, device=self.device)
+        self._check(self.lib.nfs_structure_function(self.handle, _ptr(D), _ptr(counts),
+                                                    _ptr(pairs), _ptr(status)))
+        if sync:
+            self.stream.synchronize()
+        return D, counts, pairs, status
+
+    def bin_map(self):
+        out = torch.empty((self.n, self.n // 2), dtype=torch.int32, device=self.device)
+        self._check(self.lib.nfs_bin_map(self.handle, _ptr(out)))
+        self.stream.synchronize()
+        return out
+
+    def spectrum(self, t):
+        out = torch.empty((self.n, self.n // 2, 2), dtype=torch.float32, device=self.device)
+        self._check(self.lib.nfs_copy_spectrum(self.handle, ctypes.c_int64(t), _ptr(out)))
+        self.stream.synchronize()
+        return torch.view_as_complex(out)
+
+    def reset(self):
+        self._check(self.lib.nfs_reset(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.stream.synchronize()
+            self.lib.nfs_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,109 @@
+"""The C ABI without a GPU: the library loads, exports what include/nfs.h
+declares, and its host-only entry points validate descriptors."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1209_3362_amd as nfs
+from paper_1209_3362_amd.nfs import NfsDesc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+C2_LAGS = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22,
+           23, 24, 25, 26, 27, 31, 35, 40, 45, 51, 58, 66, 75, 85, 96, 109, 124, 141, 160,
+           181, 206, 234, 265, 301, 342, 388, 440, 500]
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "nfs.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nfs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = nfs.load_library()
+    names = declared_symbols()
+    assert "nfs_plan" in names and "nfs_structure_function" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = nfs.load_library()
+    for code in range(11):
+        s = lib.nfs_status_string(code)
+        assert s and s != b"unknown status"
+    assert lib.nfs_status_string(99) == b"unknown status"
+
+
+def size(**kw):
+    args = dict(n=128, lags=[1, 2, 4], n_bins=64, in_dtype="f32", capacity=64)
+    args.update(kw)
+    return nfs.workspace_size(**args)
+
+
+def code(**kw):
+    try:
+        size(**kw)
+    except nfs.NfsError as e:
+        return nfs.status_name(e.status)
+    return "NFS_OK"
+
+
+def test_descriptor_validation():
+    assert code() == "NFS_OK"
+    assert code(n=100) == "NFS_E_SIZE"
+    assert code(n=8) == "NFS_E_SIZE"
+    assert code(n=8192) == "NFS_E_SIZE"
+    assert code(lags=[]) == "NFS_E_LAGS"
+    assert code(lags=[2, 1]) == "NFS_E_LAGS"
+    assert code(lags=[1, 1]) == "NFS_E_LAGS"
+    assert code(lags=[-1, 3]) == "NFS_E_LAGS"
+    assert code(lags=[1, 2401], capacity=3000) == "NFS_E_LAGS"
+    assert code(lags=[1, 2400], capacity=3000) == "NFS_OK"
+    assert code(n_bins=0) == "NFS_E_BINS"
+    assert code(n_bins=65) == "NFS_E_BINS"
+    assert code(n_bins=64) == "NFS_OK"
+    assert code(capacity=4) == "NFS_E_CAPACITY"
+    assert code(lags=[0], capacity=1) == "NFS_OK"
+    assert code(capacity=-1) == "NFS_E_CAPACITY"
+
+
+def test_unsupported_options_are_rejected():
+    lib = nfs.load_library()
+    arr = (ctypes.c_int32 * 1)(1)
+    for field in ("spec_dtype", "accum"):
+        d = NfsDesc(n=64, in_dtype=1, spec_dtype=0, accum=0, n_lags=1, lags=arr, n_bins=8,
+                    capacity=8, window=None)
+        setattr(d, field, 1)
+        out = ctypes.c_size_t(0)
+        assert lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out)) == 10
+    d = NfsDesc(n=64, in_dtype=5, spec_dtype=0, accum=0, n_lags=1, lags=arr, n_bins=8,
+                capacity=8, window=None)
+    out = ctypes.c_size_t(0)
+    assert lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out)) == 1
+    assert lib.nfs_plan_workspace_size(None, ctypes.byref(out)) == 1
+    assert lib.nfs_plan_workspace_size(ctypes.byref(d), None) == 1
+
+
+def test_workspace_grows_with_capacity_by_one_spectrum_each():
+    a = size(n=1024, lags=C2_LAGS, n_bins=512, in_dtype="u16", capacity=1000)
+    b = size(n=1024, lags=C2_LAGS, n_bins=512, in_dtype="u16", capacity=1001)
+    # stored modes at n = 1024 (half disc, k_x in [0, 512)) padded to 64
+    modes = 412246
+    stride = (modes + 63) // 64 * 64
+    assert b - a in (stride * 8 - 256, stride * 8, stride * 8 + 256)
+    assert 3.3e9 < a < 3.6e9
+
+
+def test_calls_on_bad_handles_fail_cleanly():
+    lib = nfs.load_library()
+    assert lib.nfs_destroy(None) == 7
+    assert lib.nfs_push_frames(None, None, 0) == 7
+    assert lib.nfs_structure_function(None, None, None, None, None) == 7
+    assert lib.nfs_reset(None) == 7
+    assert lib.nfs_last_error(None) == b"invalid handle"
+    out = ctypes.c_void_p()
+    assert lib.nfs_plan(None, None, 0, None, ctypes.byref(out)) == 1
+    assert lib.nfs_plan(None, None, 0, None, None) == 1

@@ -1,0 +1,213 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar: bin indices, bin counts and pair counts bit-exact; exact zeros (lag 0,
+the DC-only bin) exactly zero; D within 1e-4 relative of the oracle (FP32
+transforms and per-mode FP32 pair sums, FP64 bin sums).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import assert_D_close, require_gpu, run_plan, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _half_plane(a, n):
+    """Full-plane [n][n] array -> stored half-plane [n][n/2] (k_x = 0..n/2-1)."""
+    return np.asarray(a)[:, : n // 2]
+
+
+def test_c1_parity():
+    cfg = gen.config("c1")
+    say("c1 parity: 64 frames 128x128 f32, lags 1,2,4,8,16, 64 bins, seed 1")
+    f = gen.make_stack(cfg, 1)
+    ref = oracle.structure_function(f.numpy(), cfg["lags"], cfg["n_bins"])
+    D, C, P, st = run_plan(f, cfg["lags"], cfg["n_bins"], "f32")
+    assert st == 0
+    assert np.array_equal(C, ref["counts"])
+    assert np.array_equal(P, ref["pairs"])
+    assert np.all(D[:, 0] == 0.0)  # bin 0 is the DC mode alone
+    worst = assert_D_close(D, ref["D"], rtol=1e-4)
+    print("c1 worst relative error", worst)
+
+
+@pytest.mark.parametrize("n,nb", [(16, 8), (16, 1), (128, 64), (128, 7), (1024, 512), (1024, 100)])
+def test_bin_map_and_counts_bit_exact(n, nb):
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    say(f"bin map n={n} nb={nb}")
+    plan = nfs.Plan(n, [1], nb, in_dtype="f32", capacity=4)
+    got = plan.bin_map().cpu().numpy()
+    plan.close()
+    want = _half_plane(oracle.bin_index(n, nb), n)
+    assert np.array_equal(got, want)
+    # counts through the binning kernel
+    f = np.ones((3, n, n), dtype=np.float32)
+    _, C, _, _ = run_plan(f, [1], nb, "f32")
+    assert np.array_equal(C, oracle.bin_counts(oracle.bin_index(n, nb), nb))
+
+
+def test_spectra_match_oracle():
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfg = gen.config("c1", N=6)
+    say("spectra c1 frames, 6 frames")
+    f = gen.make_stack(cfg, 3)
+    spec = oracle.spectra(oracle.normalise(f.numpy())[0])
+    plan = nfs.Plan(128, [1], 64, in_dtype="f32", capacity=6)
+    plan.push(f.cuda())
+    bidx = _half_plane(oracle.bin_index(128, 64), 128)
+    stored = bidx >= 0
+    for t in range(6):
+        g = plan.spectrum(t).cpu().numpy()
+        o = _half_plane(spec[t], 128)
+        assert g[0, 0] == 128 * 128
+        assert np.all(g[~stored] == 0)
+        err = np.abs(g[stored] - o[stored]).max()
+        assert err <= 2e-6 * np.abs(o[stored]).max(), err
+    plan.close()
+
+
+def test_u16_parity():
+    cfg = gen.config("c2", n=64, N=40, lags=[1, 2, 3, 5, 8, 13, 21, 34, 39], n_bins=32)
+    say("u16 parity: 40 frames 64x64 Poisson, 9 lags, 32 bins, seed 4")
+    f = gen.make_stack(cfg, 4)
+    ref = oracle.structure_function(f.numpy().astype(np.float64), cfg["lags"], 32)
+    D, C, P, st = run_plan(f, cfg["lags"], 32, "u16")
+    assert st == 0 and np.array_equal(C, ref["counts"]) and np.array_equal(P, ref["pairs"])
+    assert_D_close(D, ref["D"], rtol=1e-4)
+
+
+def test_window_parity():
+    cfg = gen.config("c1", n=64, N=30, lags=[1, 3, 9], n_bins=32)
+    say("window parity: 30 frames 64x64 f32, Hann window")
+    f = gen.make_stack(cfg, 5)
+    w = np.outer(np.hanning(64), np.hanning(64)) + 0.05
+    w32 = w.astype(np.float32)
+    ref = oracle.structure_function(f.numpy(), cfg["lags"], 32, window=w32.astype(np.float64))
+    D, C, P, st = run_plan(f, cfg["lags"], 32, "f32", window=torch.from_numpy(w32))
+    assert st == 0
+    assert_D_close(D, ref["D"], rtol=1e-4)
+
+
+def test_ring_wrap_and_push_chunking():
+    cfg = gen.config("c1", n=64, N=100, lags=[0, 1, 2, 5, 17, 40], n_bins=32)
+    say("ring wrap: 100 frames 64x64, capacity 45 and 100, chunks 1/7/64")
+    f = gen.make_stack(cfg, 6)
+    ref = oracle.structure_function(f.numpy(), cfg["lags"], 32)
+    full = run_plan(f, cfg["lags"], 32, "f32", capacity=100)
+    assert_D_close(full[0], ref["D"], rtol=1e-4)
+    for cap, chunk in [(45, None), (41, 1), (45, 7), (100, 64), (60, 13)]:
+        D, C, P, st = run_plan(f, cfg["lags"], 32, "f32", capacity=cap, chunk=chunk)
+        assert st == 0 and np.array_equal(P, ref["pairs"])
+        assert_D_close(D, ref["D"], rtol=1e-4)
+        assert_D_close(D, full[0], rtol=1e-6)
+
+
+def test_run_twice_is_bitwise_identical():
+    cfg = gen.config("c1")
+    say("determinism: c1 twice")
+    f = gen.make_stack(cfg, 7)
+    a = run_plan(f, cfg["lags"], 64, "f32")
+    b = run_plan(f, cfg["lags"], 64, "f32")
+    assert np.array_equal(a[0], b[0])
+
+
+def test_edge_lags_and_tiny_stacks():
+    cfg = gen.config("c1", n=32, N=9, n_bins=16)
+    say("edge lags: lag 0, lags >= N, N = 9 and N = 1")
+    f = gen.make_stack(cfg, 8)
+    lags = [0, 1, 8, 9, 12]
+    ref = oracle.structure_function(f.numpy(), lags, 16)
+    D, C, P, st = run_plan(f, lags, 16, "f32", capacity=20)
+    assert P.tolist() == [9, 8, 1, 0, 0]
+    assert np.all(D[0] == 0.0)
+    assert np.all(np.isnan(D[3:]))
+    assert_D_close(D, ref["D"], rtol=1e-4)
+    D1, _, P1, _ = run_plan(f[:1], [0, 1], 16, "f32", capacity=4)
+    assert P1.tolist() == [1, 0] and np.all(D1[0] == 0) and np.all(np.isnan(D1[1]))
+
+
+def test_degenerate_frame_sets_status():
+    say("degenerate frame: an all-zero frame")
+    f = np.ones((5, 32, 32), dtype=np.float32)
+    f[2] = 0.0
+    D, C, P, st = run_plan(f, [1], 16, "f32")
+    from paper_1209_3362_amd.nfs import NFS_E_DEGENERATE_FRAME
+    assert st == NFS_E_DEGENERATE_FRAME
+
+
+@pytest.mark.parametrize("n,N", [(16, 12), (32, 10), (256, 8), (512, 6), (2048, 4), (4096, 3)])
+def test_frame_sizes(n, N):
+    cfg = gen.config("c1", n=n, N=N, n_bins=n // 2)
+    lags = sorted({1, 2, N - 1})
+    say(f"frame size n={n} N={N}")
+    f = gen.make_stack(cfg, 9)
+    ref = oracle.structure_function(f.numpy(), lags, n // 2)
+    D, C, P, st = run_plan(f, lags, n // 2, "f32")
+    assert st == 0 and np.array_equal(C, ref["counts"])
+    assert_D_close(D, ref["D"], rtol=1e-4)
+
+
+def test_cosine_closed_form_on_gpu():
+    n, N, nb = 64, 40, 32
+    modes = [(3, 5, 0.05, 0.37), (-9, 2, 0.02, 1.3), (0, 11, 0.03, 2.0)]
+    say("closed form: cosine stack 64x64")
+    f = gen.cosine_stack(n, N, modes, dtype=np.float32)
+    lags = [1, 2, 5, 11, 23]
+    D, C, P, st = run_plan(f, lags, nb, "f32")
+    bidx = oracle.bin_index(n, nb)
+    want = np.zeros((len(lags), nb))
+    for (ky, kx, eps, om) in modes:
+        b = bidx[ky % n, kx % n]
+        for i, tau in enumerate(lags):
+            want[i, b] += (eps * n * n) ** 2 * (1 - math.cos(om * tau)) / C[b]
+    hit = want > 0
+    assert np.all(np.abs(D[hit] / want[hit] - 1) < 1e-3)
+    # off-mode bins hold only FP32 transform leakage
+    assert np.all(np.abs(D[~hit]) < 1e-6 * want.max())
+
+
+@pytest.mark.parametrize("lags", [[1, 100, 545, 600], [3, 900, 1500]])
+def test_long_lags_use_narrow_tiles(lags):
+    n, N = 32, max(lags) + 60
+    cfg = gen.config("c1", n=n, N=N, n_bins=16)
+    say(f"long lags {lags}, N={N}, 32x32")
+    f = gen.make_stack(cfg, 10)
+    ref = oracle.structure_function(f.numpy(), lags, 16)
+    D, C, P, st = run_plan(f, lags, 16, "f32")
+    assert np.array_equal(P, ref["pairs"])
+    assert_D_close(D, ref["D"], rtol=1e-4)
+
+
+def test_more_lags_than_one_launch():
+    n, N = 32, 260
+    lags = list(range(0, 200))
+    cfg = gen.config("c1", n=n, N=N, n_bins=16)
+    say("200 lags (two lag groups), N=260, 32x32")
+    f = gen.make_stack(cfg, 11)
+    ref = oracle.structure_function(f.numpy(), lags, 16)
+    D, C, P, st = run_plan(f, lags, 16, "f32")
+    assert np.array_equal(P, ref["pairs"])
+    assert_D_close(D, ref["D"], rtol=1e-4)
+
+
+def test_bad_calls_raise():
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    say("argument errors on the device path")
+    plan = nfs.Plan(32, [1], 16, in_dtype="u16", capacity=8)
+    with pytest.raises(ValueError):
+        plan.push(torch.zeros((2, 32, 32), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.push(torch.zeros((2, 16, 16), dtype=torch.uint16, device="cuda"))
+    with pytest.raises(nfs.NfsError):
+        plan.spectrum(0)  # nothing pushed yet
+    plan.close()
+    with pytest.raises(nfs.NfsError):
+        nfs.Plan(32, [1, 1], 16, in_dtype="u16", capacity=8)
