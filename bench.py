@@ -1,0 +1,172 @@
+"""Throughput of the structure-function path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: 1000 uint16 frames of 1024x1024 (12-bit camera model, Poisson
+noise), 50 log-spaced lags 1..500, 512 |q| rings. The frames are drawn on
+the GPU and are resident in HBM before timing. One step is the whole path
+on that stack: reset the sums, push the 1000 frames (normalise + 2D
+transform + store), accumulate the lag pairs, bin into D(q, tau). Prints one
+JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "frame-pairs/sec and HBM GB/s for D(q,tau), 1024^2 x 1000 frames, 1 GPU"
+# MI355X published peaks and the non-packed FP32 VALU rate derived from the
+# unit counts: 256 CUs x 64 lanes x 2.4 GHz lane-instructions per second.
+HBM_PEAK_GBPS = 8000.0
+VALU_LANE_OPS = 256 * 64 * 2.4e9
+FP32_FMA_PEAK_TFLOPS = VALU_LANE_OPS * 2 / 1e12  # 78.6
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-frames", type=int, default=80)
+    return ap.parse_args()
+
+
+def frame_pairs(N, lags):
+    return sum(max(0, N - t) for t in lags)
+
+
+def cpu_baseline(frames_gpu, cfg, n_frames):
+    """Time the FP64 oracle on the first `n_frames` frames, lags < n_frames."""
+    import numpy as np
+    import oracle
+    lags = [t for t in cfg["lags"] if t < n_frames]
+    sample = frames_gpu[:n_frames].cpu().numpy().astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.structure_function(sample, lags, cfg["n_bins"])
+    dt = time.perf_counter() - t0
+    fp = frame_pairs(n_frames, lags)
+    return {"value": fp / dt, "unit": "frame-pairs/s", "cores": 1, "kind": "oracle",
+            "sample": (f"first {n_frames} frames of the timed stack, the {len(lags)} of its "
+                       f"lags below {n_frames} ({fp} frame-pairs), 512 rings, FP64 NumPy "
+                       f"full-plane oracle, {dt:.1f} s on one host thread")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import gen
+    import paper_1209_3362_amd as nfs
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = gen.config("c2")
+    n, N, lags, nb = cfg["n"], cfg["N"], cfg["lags"], cfg["n_bins"]
+    frames = gen.make_stack(cfg, args.seed, device="cuda")
+    torch.cuda.synchronize()
+
+    plan = nfs.Plan(n, lags, nb, in_dtype="u16", capacity=N, device=dev)
+    stream = plan.stream
+    out = plan.empty_outputs()
+    M = plan.modes
+    pairs = frame_pairs(N, lags)
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        plan.reset()
+        plan.push(frames)
+        if ev:
+            ev[1].record(stream)
+        plan.accumulate()
+        if ev:
+            ev[2].record(stream)
+        plan.structure_function(sync=False, out=out)
+        if ev:
+            ev[3].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    ms_fft = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    ms_pair = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    ms_bin = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
+    ms_step = wall * 1e3 / args.steps
+
+    D = out[0].cpu()
+    assert bool(torch.isfinite(D).all()), "non-finite D"
+    st = int(out[3].item())
+
+    # Algorithmic traffic of one step: frames read once, each stored mode
+    # (half disc, the modes any ring uses) written once and read once, per-lag
+    # sums written and read once.
+    bytes_frames = N * n * n * 2
+    bytes_spec = N * M * 8
+    bytes_sums = len(lags) * M * 4
+    alg_bytes = bytes_frames + 2 * bytes_spec + 2 * bytes_sums
+    pair_k = pairs * M
+    # Pair kernel: per pair and mode 2 subtractions + 2 FMAs = 6 FLOP
+    # (4 VALU lane-instructions).
+    pair_tflops = 6.0 * pair_k / (ms_pair * 1e-3) / 1e12
+
+    rec = {
+        "metric": METRIC,
+        "value": pairs / (ms_step * 1e-3),
+        "unit": "frame-pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1000 uint16 frames 1024x1024, 50 log-spaced lags 1..500, "
+                               "512 |q| rings, seed %d" % args.seed,
+                   "frames": N, "n": n, "lags": len(lags), "n_bins": nb,
+                   "frame_pairs": pairs, "stored_modes": M, "parallelism": "single GPU"},
+        "hbm_gbps_algorithmic": alg_bytes / (ms_step * 1e-3) / 1e9,
+        "stage_ms": {"normalise_fft_store": ms_fft, "lag_pairs": ms_pair, "bin": ms_bin},
+        "status": st,
+        "roofline": {
+            "kernel": "pair_kernel (lag-pair accumulator)",
+            "bound": "alu",
+            "achieved": pair_tflops,
+            "peak": FP32_FMA_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": pair_tflops / FP32_FMA_PEAK_TFLOPS,
+            "traffic": None,
+            "valu_issue_frac": 4.0 * pair_k / (ms_pair * 1e-3) / VALU_LANE_OPS,
+        },
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(frames, cfg, args.cpu_frames)
+    plan.close()
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

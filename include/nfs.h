@@ -92,9 +92,9 @@ typedef struct {
 } nfs_desc;
 
 /* Bytes of device workspace nfs_plan needs for `desc`. Host only; enqueues
- * nothing. With desc->capacity == 0 the size for a ring of
- * max(largest lag + 1, 64) spectra is returned. Memory plan made before any
- * frame is processed, as in the processing section. */
+ * nothing. With desc->capacity == 0 the size for a ring of (largest lag + 64)
+ * spectra is returned. Memory plan made before any frame is processed, as in
+ * the processing section. */
 nfs_status nfs_plan_workspace_size(const nfs_desc* desc, size_t* bytes);
 
 /* Create a plan. `workspace` is a device buffer of `bytes` bytes, 256-byte
@@ -113,6 +113,11 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes,
  * later pair still needs. Frame indices continue across calls. count == 0 is
  * a no-op. */
 nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count);
+
+/* Accumulate the pair sums of every frame pushed so far (enqueued). Needed
+ * only to split the work, e.g. to overlap it with acquisition or to time it:
+ * nfs_structure_function does it implicitly. */
+nfs_status nfs_accumulate(nfs_handle h);
 
 /* Finish the pair sums for every frame pushed so far and write, all on the
  * device:

@@ -64,8 +64,9 @@ struct ColCfg {
 // for k = 0..H-1 (the real-input split; X[H] is never binned).
 template <int N, typename T, bool WIN>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
-    const T* __restrict__ frames, const float* __restrict__ window, int64_t total_rows,
-    float2* __restrict__ inter, double* __restrict__ rowsum, const float2* __restrict__ tw) {
+    const T* __restrict__ frames, const T* __restrict__ ref, const float* __restrict__ window,
+    int64_t total_rows, float2* __restrict__ inter, double* __restrict__ rowsum,
+    const float2* __restrict__ tw) {
   using C = RowCfg<N>;
   constexpr int H = C::H, P1 = C::P1, P2 = C::P2, Q = C::Q, R = C::R;
   constexpr int PITCH = C::PITCH, THREADS = C::THREADS, TILES = C::TILES;
@@ -91,10 +92,20 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
         const uint32_t w = *reinterpret_cast<const uint32_t*>(src + 2 * j);
         a = float(w & 0xffffu);
         b = float(w >> 16);
+        if (ref) {  // integer difference: exact in FP32
+          const uint32_t r = *reinterpret_cast<const uint32_t*>(ref + int64_t(y) * N + 2 * j);
+          a -= float(r & 0xffffu);
+          b -= float(r >> 16);
+        }
       } else {
         const float2 w = *reinterpret_cast<const float2*>(src + 2 * j);
         a = w.x;
         b = w.y;
+        if (ref) {
+          const float2 r = *reinterpret_cast<const float2*>(ref + int64_t(y) * N + 2 * j);
+          a -= r.x;
+          b -= r.y;
+        }
       }
       if constexpr (WIN) {
         const float2 ww = *reinterpret_cast<const float2*>(window + int64_t(y) * N + 2 * j);
@@ -105,8 +116,9 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
     v[j2] = make_float2(a, b);
     s += double(a) + double(b);
   }
-  // Exact row sum (integer pixels sum exactly in double), butterfly over the
-  // P1 lanes of the row: every lane ends with the same value.
+  // Row sum of what was transformed (exact in double for integer pixels),
+  // butterfly over the P1 lanes of the row: every lane ends with the same
+  // value.
 #pragma unroll
   for (int o = P1 / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, P1);
   if (valid && j1 == 0) rowsum[grow] = s;
@@ -170,12 +182,13 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
 // Column pass over CW columns of one frame: DFT_N over the rows, scale by
 // n^2 / sum(u) (the zero-frequency value of the row-pass output), set
 // I(0) = n^2 exactly and store the modes with k_x < row_width[r].
-template <int N>
+template <int N, bool REF>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
     const float2* __restrict__ inter, const double* __restrict__ rowsum, int64_t t0,
     int64_t capacity, int64_t mode_stride, const int32_t* __restrict__ row_width,
     const int32_t* __restrict__ row_offset, const float2* __restrict__ tw,
-    float2* __restrict__ ring, int32_t* __restrict__ status) {
+    float2* __restrict__ ring, float2* __restrict__ refspec, double* __restrict__ refscal,
+    int32_t* __restrict__ status) {
   using C = ColCfg<N>;
   constexpr int P1 = C::P1, P2 = C::P2, Q = C::Q, CP = C::CP, CW = C::CW;
   constexpr int THREADS = C::THREADS, GROUPS = C::GROUPS, TILES = C::TILES;
@@ -200,12 +213,31 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
   for (int o = WAVE / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, WAVE);
   if ((tid & 63) == 0) red[tid >> 6] = s;
   __syncthreads();
-  double total = 0.0;
+  double part = 0.0;
 #pragma unroll
-  for (int w = 0; w < NWAVES; ++w) total += red[w];
+  for (int w = 0; w < NWAVES; ++w) part += red[w];
+  // REF: the rows were the reference image itself; its transform is stored
+  // unscaled in refspec and its sum S_ref and scale n^2/S_ref in refscal.
+  // Otherwise the rows were (image - reference): the image sum is
+  // S_ref + part, sigma = n^2 / sum, and the stored value is
+  // sigma * F[image - reference] + (sigma - sigma_ref) * F[reference]
+  // = I_t - sigma_ref * F[reference], fluctuation-sized.
+  const double total = REF ? part : refscal[0] + part;
   const bool bad = !(total > 0.0) || !isfinite(total);
-  const float scale = bad ? 0.f : float(double(N) * double(N) / total);
-  if (bad && tid == 0) atomicOr(status, 1);
+  const double sigma = bad ? 0.0 : double(N) * double(N) / total;
+  float scale, dscale;
+  if constexpr (REF) {
+    scale = 1.f;
+    dscale = 0.f;
+    if (blockIdx.x == 0 && tid == 0) {
+      refscal[0] = total;
+      refscal[1] = sigma;
+    }
+  } else {
+    scale = float(sigma);
+    dscale = float(sigma - refscal[1]);
+    if (bad && tid == 0) atomicOr(status, 1);
+  }
 
   const float2* src = inter + (int64_t(f) * TILES + tile) * N * 8 + c0 + c;
   float2 v[P2];
@@ -221,8 +253,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
   });
   __syncthreads();
 
-  const int64_t slot = (t0 + f) % capacity;
-  float2* dst = ring + slot * mode_stride;
+  float2* dst = REF ? refspec : ring + ((t0 + f) % capacity) * mode_stride;
   const int kx = kx0 + c;
   static_for<Q>([&](auto QQ) {
     constexpr int q = decltype(QQ)::value;
@@ -235,76 +266,99 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
       constexpr int k1 = decltype(K1)::value;
       const int r = k2 + P2 * k1;
       float2 X = w[bitrev<P1>(k1)];
-      X.x *= scale;
-      X.y *= scale;
-      if (r == 0 && kx == 0) X = make_float2(float(N) * float(N), 0.f);
-      if (kx < row_width[r]) dst[row_offset[r] + kx] = X;
+      if (kx < row_width[r]) {
+        const int64_t at = row_offset[r] + kx;
+        if constexpr (!REF) {
+          const float2 R = refspec[at];
+          X.x = fmaf(dscale, R.x, scale * X.x);
+          X.y = fmaf(dscale, R.y, scale * X.y);
+          // I_t(0) = n^2 for every frame, so its offset from the reference is 0.
+          if (at == 0) X = make_float2(0.f, 0.f);
+        }
+        dst[at] = X;
+      }
     });
   });
 }
 
 template <int N, typename T, bool WIN>
-hipError_t row_launch(const void* frames, const float* window, int nframes, float2* inter,
-                      double* rowsum, const float2* tw, hipStream_t s) {
+hipError_t row_launch(const void* frames, const void* ref, const float* window, int nframes,
+                      float2* inter, double* rowsum, const float2* tw, hipStream_t s) {
   using C = RowCfg<N>;
   const int64_t rows = int64_t(nframes) * N;
   const int64_t blocks = (rows + C::R - 1) / C::R;
   hipLaunchKernelGGL((row_pass_kernel<N, T, WIN>), dim3(unsigned(blocks)), dim3(C::THREADS),
-                     0, s, static_cast<const T*>(frames), window, rows, inter, rowsum, tw);
+                     0, s, static_cast<const T*>(frames), static_cast<const T*>(ref), window,
+                     rows, inter, rowsum, tw);
   return hipGetLastError();
 }
 
 template <int N>
-hipError_t row_dispatch(int in_dtype, const void* frames, const float* window, int nframes,
-                        float2* inter, double* rowsum, const float2* tw, hipStream_t s) {
+hipError_t row_dispatch(int in_dtype, const void* frames, const void* ref, const float* window,
+                        int nframes, float2* inter, double* rowsum, const float2* tw,
+                        hipStream_t s) {
   if (in_dtype == 0) {
-    return window ? row_launch<N, uint16_t, true>(frames, window, nframes, inter, rowsum, tw, s)
-                  : row_launch<N, uint16_t, false>(frames, window, nframes, inter, rowsum, tw, s);
+    return window ? row_launch<N, uint16_t, true>(frames, ref, window, nframes, inter, rowsum,
+                                                  tw, s)
+                  : row_launch<N, uint16_t, false>(frames, ref, window, nframes, inter, rowsum,
+                                                   tw, s);
   }
-  return window ? row_launch<N, float, true>(frames, window, nframes, inter, rowsum, tw, s)
-                : row_launch<N, float, false>(frames, window, nframes, inter, rowsum, tw, s);
+  return window ? row_launch<N, float, true>(frames, ref, window, nframes, inter, rowsum, tw, s)
+                : row_launch<N, float, false>(frames, ref, window, nframes, inter, rowsum, tw, s);
 }
 
 template <int N>
-hipError_t col_launch(const float2* inter, const double* rowsum, int nframes, int64_t t0,
-                      int64_t capacity, int64_t mode_stride, const int32_t* row_width,
-                      const int32_t* row_offset, const float2* tw, float2* ring,
-                      int32_t* status, hipStream_t s) {
+hipError_t col_launch(bool reference, const float2* inter, const double* rowsum, int nframes,
+                      int64_t t0, int64_t capacity, int64_t mode_stride,
+                      const int32_t* row_width, const int32_t* row_offset, const float2* tw,
+                      float2* ring, float2* refspec, double* refscal, int32_t* status,
+                      hipStream_t s) {
   using C = ColCfg<N>;
   const int64_t blocks = int64_t(nframes) * C::GROUPS;
-  hipLaunchKernelGGL(col_pass_kernel<N>, dim3(unsigned(blocks)), dim3(C::THREADS), 0, s,
-                     inter, rowsum, t0, capacity, mode_stride, row_width, row_offset, tw,
-                     ring, status);
+  if (reference) {
+    hipLaunchKernelGGL((col_pass_kernel<N, true>), dim3(unsigned(blocks)), dim3(C::THREADS), 0,
+                       s, inter, rowsum, t0, capacity, mode_stride, row_width, row_offset, tw,
+                       ring, refspec, refscal, status);
+  } else {
+    hipLaunchKernelGGL((col_pass_kernel<N, false>), dim3(unsigned(blocks)), dim3(C::THREADS), 0,
+                       s, inter, rowsum, t0, capacity, mode_stride, row_width, row_offset, tw,
+                       ring, refspec, refscal, status);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const float* window,
-                           int nframes, float2* inter, double* rowsum, const float2* tw,
-                           hipStream_t s) {
+hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* ref,
+                           const float* window, int nframes, float2* inter, double* rowsum,
+                           const float2* tw, hipStream_t s) {
+#define NFS_ROW_CASE(NN) \
+  case NN:               \
+    return row_dispatch<NN>(in_dtype, frames, ref, window, nframes, inter, rowsum, tw, s);
   switch (n) {
-    case 16: return row_dispatch<16>(in_dtype, frames, window, nframes, inter, rowsum, tw, s);
-    case 32: return row_dispatch<32>(in_dtype, frames, window, nframes, inter, rowsum, tw, s);
-    case 64: return row_dispatch<64>(in_dtype, frames, window, nframes, inter, rowsum, tw, s);
-    case 128: return row_dispatch<128>(in_dtype, frames, window, nframes, inter, rowsum, tw, s);
-    case 256: return row_dispatch<256>(in_dtype, frames, window, nframes, inter, rowsum, tw, s);
-    case 512: return row_dispatch<512>(in_dtype, frames, window, nframes, inter, rowsum, tw, s);
-    case 1024: return row_dispatch<1024>(in_dtype, frames, window, nframes, inter, rowsum, tw, s);
-    case 2048: return row_dispatch<2048>(in_dtype, frames, window, nframes, inter, rowsum, tw, s);
-    case 4096: return row_dispatch<4096>(in_dtype, frames, window, nframes, inter, rowsum, tw, s);
+    NFS_ROW_CASE(16)
+    NFS_ROW_CASE(32)
+    NFS_ROW_CASE(64)
+    NFS_ROW_CASE(128)
+    NFS_ROW_CASE(256)
+    NFS_ROW_CASE(512)
+    NFS_ROW_CASE(1024)
+    NFS_ROW_CASE(2048)
+    NFS_ROW_CASE(4096)
     default: return hipErrorInvalidValue;
   }
+#undef NFS_ROW_CASE
 }
 
-hipError_t launch_col_pass(int n, const float2* inter, const double* rowsum, int nframes,
-                           int64_t t0, int64_t capacity, int64_t mode_stride,
+hipError_t launch_col_pass(int n, bool reference, const float2* inter, const double* rowsum,
+                           int nframes, int64_t t0, int64_t capacity, int64_t mode_stride,
                            const int32_t* row_width, const int32_t* row_offset,
-                           const float2* tw, float2* ring, int32_t* status, hipStream_t s) {
-#define NFS_COL_CASE(NN)                                                                 \
-  case NN:                                                                               \
-    return col_launch<NN>(inter, rowsum, nframes, t0, capacity, mode_stride, row_width, \
-                          row_offset, tw, ring, status, s);
+                           const float2* tw, float2* ring, float2* refspec, double* refscal,
+                           int32_t* status, hipStream_t s) {
+#define NFS_COL_CASE(NN)                                                                   \
+  case NN:                                                                                 \
+    return col_launch<NN>(reference, inter, rowsum, nframes, t0, capacity, mode_stride,   \
+                          row_width, row_offset, tw, ring, refspec, refscal, status, s);
   switch (n) {
     NFS_COL_CASE(16)
     NFS_COL_CASE(32)

@@ -29,7 +29,10 @@ struct nfs_plan_s {
   float2* inter = nullptr;
   double* rowsum = nullptr;
   float* acc = nullptr;
-  int32_t* status = nullptr;
+  int32_t* status = nullptr;    // bit 0: a degenerate frame was pushed
+  double* refscal = nullptr;    // {S_ref, sigma_ref} of the reference frame
+  void* ref = nullptr;          // reference frame: first frame of the sequence
+  float2* refspec = nullptr;    // its transform on the stored modes
   float2* tw = nullptr;
   int32_t* width = nullptr;
   int32_t* offset = nullptr;
@@ -145,6 +148,9 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->width = reinterpret_cast<int32_t*>(h->ws + L.off_width);
   h->offset = reinterpret_cast<int32_t*>(h->ws + L.off_offset);
   h->lags = reinterpret_cast<int32_t*>(h->ws + L.off_lags);
+  h->refscal = reinterpret_cast<double*>(h->ws + L.off_status + 8);
+  h->ref = h->ws + L.off_ref;
+  h->refspec = reinterpret_cast<float2*>(h->ws + L.off_refspec);
 
   const std::vector<float> tw = nfs::twiddle_table(L.n);
   hipError_t e = hipMemcpyAsync(h->tw, tw.data(), tw.size() * sizeof(float),
@@ -191,24 +197,46 @@ nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count) {
     if (b > L.batch) b = L.batch;
     if (b > room) b = room;
     // Pushing frames [t_pushed, t_pushed + b) evicts frames up to
-    // t_pushed + b - 1 - capacity; pending pairs need frames from
-    // t_done - max_lag on.
-    if (h->t_pushed + b - L.capacity > h->t_done - L.max_lag) {
+    // t_pushed + b - 1 - capacity; pending pairs need the frames from
+    // max(0, t_done - max_lag) on.
+    const int64_t needed = h->t_done - L.max_lag > 0 ? h->t_done - L.max_lag : 0;
+    if (h->t_pushed + b - L.capacity > needed) {
       nfs_status st = flush_pairs(h);
       if (st != NFS_OK) return st;
     }
     const char* src = static_cast<const char*>(frames) + size_t(i) * frame_bytes;
-    hipError_t e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->window, int(b), h->inter,
-                                        h->rowsum, h->tw, h->stream);
+    hipError_t e = hipSuccess;
+    if (h->t_pushed == 0) {
+      // The first frame of the sequence becomes the reference subtracted
+      // from every frame before its transform; differences of transforms
+      // are unchanged, but the stored values no longer carry the static
+      // image, whose low-q coefficients would swamp FP32.
+      e = hipMemcpyAsync(h->ref, src, frame_bytes, hipMemcpyDeviceToDevice, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "reference copy");
+      e = nfs::launch_row_pass(L.n, L.in_dtype, h->ref, nullptr, h->window, 1, h->inter,
+                               h->rowsum, h->tw, h->stream);
+      if (e == hipSuccess)
+        e = nfs::launch_col_pass(L.n, true, h->inter, h->rowsum, 1, 0, L.capacity,
+                                 L.mode_stride, h->width, h->offset, h->tw, h->ring,
+                                 h->refspec, h->refscal, h->status, h->stream);
+      if (e != hipSuccess) return hip_fail(h, e, "reference transform launch");
+    }
+    e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->ref, h->window, int(b), h->inter,
+                             h->rowsum, h->tw, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
-    e = nfs::launch_col_pass(L.n, h->inter, h->rowsum, int(b), h->t_pushed, L.capacity,
-                             L.mode_stride, h->width, h->offset, h->tw, h->ring, h->status,
-                             h->stream);
+    e = nfs::launch_col_pass(L.n, false, h->inter, h->rowsum, int(b), h->t_pushed, L.capacity,
+                             L.mode_stride, h->width, h->offset, h->tw, h->ring, h->refspec,
+                             h->refscal, h->status, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
     h->t_pushed += b;
     i += b;
   }
   return NFS_OK;
+}
+
+nfs_status nfs_accumulate(nfs_handle h) {
+  if (!is_live(h)) return NFS_E_STATE;
+  return flush_pairs(h);
 }
 
 nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
@@ -265,8 +293,9 @@ nfs_status nfs_copy_spectrum(nfs_handle h, int64_t t, float* out) {
   if (t < 0 || t >= h->t_pushed || t < h->t_pushed - h->L.capacity)
     return fail(h, NFS_E_STATE, "frame is not in the ring");
   hipError_t e = nfs::launch_expand_spectrum(h->L.n, h->ring, t % h->L.capacity,
-                                             h->L.mode_stride, h->width, h->offset,
-                                             reinterpret_cast<float2*>(out), h->stream);
+                                             h->L.mode_stride, h->width, h->offset, h->refspec,
+                                             h->refscal, reinterpret_cast<float2*>(out),
+                                             h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "expand launch");
   return NFS_OK;
 }

@@ -158,6 +158,8 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_width = take(size_t(o.n) * 4);
   o.off_offset = take(size_t(o.n) * 4);
   o.off_lags = take(size_t(o.n_lags) * 4);
+  o.off_ref = take(size_t(o.n) * o.n * (o.in_dtype == NFS_IN_U16 ? 2 : 4));
+  o.off_refspec = take(size_t(o.mode_stride) * 8);
   o.off_ring = off;
   const size_t spec_bytes = size_t(o.mode_stride) * 8;
 

@@ -69,6 +69,7 @@ struct Layout {
   // Byte offsets into the workspace.
   size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_acc = 0;
   size_t off_status = 0, off_tw = 0, off_width = 0, off_offset = 0;
+  size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
   size_t off_lags = 0, total = 0;
 };
 

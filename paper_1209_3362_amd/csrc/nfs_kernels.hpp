@@ -9,23 +9,28 @@
 namespace nfs {
 
 // Row pass (per image row: real-to-complex transform of n pixels to the
-// n/2 half-plane coefficients k_x = 0..n/2-1) plus exact per-row pixel sums.
-// frames: [nframes][n][n] of u16 (in_dtype 0) or f32 (1); window: [n][n] or
-// null. Writes inter [nframes][n/16][n][8] complex (8-column tiles) and
-// rowsum [nframes][n] double.
-hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const float* window,
-                           int nframes, float2* inter, double* rowsum,
+// n/2 half-plane coefficients k_x = 0..n/2-1) plus per-row sums of what was
+// transformed. frames: [nframes][n][n] of u16 (in_dtype 0) or f32 (1);
+// ref: [n][n] of the same type subtracted from every frame first, or null;
+// window: [n][n] multiplied in after the subtraction, or null. Writes inter
+// [nframes][n/16][n][8] complex (8-column tiles) and rowsum [nframes][n].
+hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* ref,
+                           const float* window, int nframes, float2* inter, double* rowsum,
                            const float2* tw, hipStream_t s);
 
-// Column pass (per column k_x: complex transform over the n rows), scaling
-// by n^2 / (frame sum), I(0) := n^2, and store of the stored modes of each
-// frame f into ring slot (t0 + f) mod capacity. Frames with a non-positive
-// or non-finite sum set bit 0 of *status and are stored with scale 0.
-hipError_t launch_col_pass(int n, const float2* inter, const double* rowsum,
-                           int nframes, int64_t t0, int64_t capacity,
-                           int64_t mode_stride, const int32_t* row_width,
-                           const int32_t* row_offset, const float2* tw,
-                           float2* ring, int32_t* status, hipStream_t s);
+// Column pass (per column k_x: complex transform over the n rows).
+// reference == true: the rows are the reference image (one frame); store its
+// transform unscaled in refspec and refscal = {S_ref, n^2/S_ref}.
+// reference == false: the rows are (frame - reference); with
+// sigma = n^2 / (S_ref + row sums) store
+// sigma * X + (sigma - sigma_ref) * refspec, 0 at k = 0, for frame f into
+// ring slot (t0 + f) mod capacity. A frame whose sum is not positive and
+// finite sets bit 0 of *status and gets sigma = 0.
+hipError_t launch_col_pass(int n, bool reference, const float2* inter, const double* rowsum,
+                           int nframes, int64_t t0, int64_t capacity, int64_t mode_stride,
+                           const int32_t* row_width, const int32_t* row_offset,
+                           const float2* tw, float2* ring, float2* refspec, double* refscal,
+                           int32_t* status, hipStream_t s);
 
 // Lag-pair accumulation for target frames [T0, T1) and the lags
 // lags[0..n_lags): acc[l][m] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2 over
@@ -53,10 +58,11 @@ hipError_t launch_fill_u32(void* dst, size_t words, uint32_t value, hipStream_t 
 // Writes the bin of every half-plane mode to map [n][n/2].
 hipError_t launch_bin_map(int n, int n_bins, int32_t* map, hipStream_t s);
 
-// Expands ring slot `slot` to out [n][n/2] complex, zeros where not stored.
+// Expands ring slot `slot` to the spectrum out [n][n/2] complex: stored
+// value + sigma_ref * refspec, I(0) = n^2, zeros where not stored.
 hipError_t launch_expand_spectrum(int n, const float2* ring, int64_t slot,
                                   int64_t mode_stride, const int32_t* row_width,
-                                  const int32_t* row_offset, float2* out,
-                                  hipStream_t s);
+                                  const int32_t* row_offset, const float2* refspec,
+                                  const double* refscal, float2* out, hipStream_t s);
 
 }  // namespace nfs

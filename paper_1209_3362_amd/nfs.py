@@ -67,6 +67,7 @@ def load_library():
         "nfs_plan_workspace_size": (i32, [ctypes.POINTER(NfsDesc), ctypes.POINTER(sz)]),
         "nfs_plan": (i32, [ctypes.POINTER(NfsDesc), P, sz, P, ctypes.POINTER(P)]),
         "nfs_push_frames": (i32, [P, P, i64]),
+        "nfs_accumulate": (i32, [P]),
         "nfs_structure_function": (i32, [P, P, P, P, P]),
         "nfs_reset": (i32, [P]),
         "nfs_destroy": (i32, [P]),
@@ -171,12 +172,22 @@ class Plan:
                                              ctypes.c_int64(frames.shape[0])))
         return self
 
-    def structure_function(self, sync=True):
+    def accumulate(self):
+        """Sum the pairs of every frame pushed so far (enqueued)."""
+        self._check(self.lib.nfs_accumulate(self.handle))
+        return self
+
+    def empty_outputs(self):
         L, nb = len(self.lags), self.n_bins
-        D = torch.empty((L, nb), dtype=torch.float64, device=self.device)
-        counts = torch.empty(nb, dtype=torch.int64, device=self.device)
-        pairs = torch.empty(L, dtype=torch.int64, device=self.device)
-        status = torch.empty(1, dtype=torch.int32, device=self.device)
+        return (torch.empty((L, nb), dtype=torch.float64, device=self.device),
+                torch.empty(nb, dtype=torch.int64, device=self.device),
+                torch.empty(L, dtype=torch.int64, device=self.device),
+                torch.empty(1, dtype=torch.int32, device=self.device))
+
+    def structure_function(self, sync=True, out=None):
+        if out is None:
+            out = self.empty_outputs()
+        D, counts, pairs, status = out
         self._check(self.lib.nfs_structure_function(self.handle, _ptr(D), _ptr(counts),
                                                     _ptr(pairs), _ptr(status)))
         if sync:
