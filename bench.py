@@ -35,6 +35,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=80)
+    ap.add_argument("--frames-cache", default=None,
+                    help="load the stack from this .npy if it exists, else draw it and "
+                         "save it there (lets profiler runs skip the generator)")
     return ap.parse_args()
 
 
@@ -75,7 +78,16 @@ def main():
     torch.cuda.set_device(dev)
     cfg = gen.config("c2")
     n, N, lags, nb = cfg["n"], cfg["N"], cfg["lags"], cfg["n_bins"]
-    frames = gen.make_stack(cfg, args.seed, device="cuda")
+    frames = None
+    if args.frames_cache and os.path.exists(args.frames_cache):
+        import numpy as np
+        arr = np.load(args.frames_cache)
+        frames = torch.from_numpy(arr.view(np.int16)).to(dev).view(torch.uint16)
+    if frames is None:
+        frames = gen.make_stack(cfg, args.seed, device="cuda")
+        if args.frames_cache:
+            import numpy as np
+            np.save(args.frames_cache, frames.view(torch.int16).cpu().numpy().view(np.uint16))
     torch.cuda.synchronize()
 
     plan = nfs.Plan(n, lags, nb, in_dtype="u16", capacity=N, device=dev)

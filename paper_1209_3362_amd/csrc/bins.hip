@@ -8,7 +8,8 @@
 // walks the ring row by row with no per-mode table. Each half-plane mode
 // stands for itself and its mirror -k (weight 2) except on k_x = 0, where
 // both k and -k are stored (weight 1). Sums are FP64 in a fixed order
-// (per-thread rows, then a fixed LDS tree), so D is bitwise reproducible.
+// (per-thread rows, a fixed butterfly per wave, waves in index order), so D
+// is bitwise reproducible.
 #include "nfs.h"
 #include "nfs_device.hpp"
 #include "nfs_kernels.hpp"
@@ -17,7 +18,18 @@ namespace nfs {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
 constexpr int kMaxRowsPerThread = 16;  // 2 * 2047 + 1 rows at n = 4096
+constexpr int kLagChunk = 8;           // lags summed per pass over the ring
+
+// Sum over the 64 lanes of a wave in a fixed butterfly order; every lane
+// gets the same value.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
 
 __global__ __launch_bounds__(kThreads) void bin_kernel(
     int n, int nb, const float* __restrict__ acc, int64_t mode_stride,
@@ -25,10 +37,11 @@ __global__ __launch_bounds__(kThreads) void bin_kernel(
     int64_t n_frames, const int32_t* __restrict__ status, double* __restrict__ D,
     int64_t* __restrict__ counts, int64_t* __restrict__ pairs, int32_t* __restrict__ status_out) {
   using namespace dev;
-  __shared__ double red[kThreads];
-  __shared__ long long redc[kThreads];
+  __shared__ double red[kWaves][kLagChunk];
+  __shared__ long long redc[kWaves];
   const int b = blockIdx.x;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
 
   int64_t lo, hi;
   ring_bounds_dev(n, nb, b, &lo, &hi);
@@ -55,37 +68,44 @@ __global__ __launch_bounds__(kThreads) void bin_kernel(
       }
     }
   }
-  redc[tid] = cnt;
+  cnt = wave_sum(cnt);
+  if (lane == 0) redc[wave] = cnt;
   __syncthreads();
-  for (int w = kThreads / 2; w > 0; w >>= 1) {
-    if (tid < w) redc[tid] += redc[tid + w];
-    __syncthreads();
-  }
-  const long long C = redc[0];
+  long long C = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) C += redc[w];
   if (tid == 0 && counts) counts[b] = C;
 
-  for (int l = 0; l < n_lags; ++l) {
-    const float* src = acc + int64_t(l) * mode_stride;
-    double s = 0.0;
+  for (int l0 = 0; l0 < n_lags; l0 += kLagChunk) {
+    double s[kLagChunk];
+#pragma unroll
+    for (int j = 0; j < kLagChunk; ++j) s[j] = 0.0;
 #pragma unroll
     for (int i = 0; i < kMaxRowsPerThread; ++i) {
       for (int kx = kxa[i]; kx < kxb[i]; ++kx) {
-        const double v = double(src[roff[i] + kx]);
-        s += kx == 0 ? v : 2.0 * v;
+        const double wgt = kx == 0 ? 1.0 : 2.0;
+        const float* src = acc + int64_t(l0) * mode_stride + roff[i] + kx;
+#pragma unroll
+        for (int j = 0; j < kLagChunk; ++j)
+          if (l0 + j < n_lags) s[j] += wgt * double(src[int64_t(j) * mode_stride]);
       }
     }
-    __syncthreads();  // red[] of the previous lag has been read
-    red[tid] = s;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kLagChunk; ++j) {
+      const double v = wave_sum(s[j]);
+      if (lane == 0) red[wave][j] = v;
     }
-    if (tid == 0) {
+    __syncthreads();
+    if (tid < kLagChunk && l0 + tid < n_lags) {
+      double tot = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) tot += red[w][tid];
+      const int l = l0 + tid;
       const int64_t np = n_frames - lags[l] > 0 ? n_frames - lags[l] : 0;
-      D[int64_t(l) * nb + b] = (np > 0 && C > 0) ? red[0] / (double(C) * double(np))
+      D[int64_t(l) * nb + b] = (np > 0 && C > 0) ? tot / (double(C) * double(np))
                                                  : __builtin_nan("");
     }
+    __syncthreads();  // red[] is reused by the next chunk
   }
 
   if (b == 0) {

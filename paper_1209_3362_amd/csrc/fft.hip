@@ -41,8 +41,10 @@ struct RowCfg {
   static constexpr int P2 = H / P1;
   static constexpr int Q = P2 / P1;
   static constexpr int PITCH = P2 * (P1 + 1) + 4;    // LDS complex values per row
-  static constexpr int R = fit_rows(256 / P1, PITCH);
+  static constexpr int R0 = fit_rows(256 / P1, PITCH);
+  static constexpr int R = R0 < N ? R0 : N;          // rows per workgroup
   static constexpr int THREADS = R * P1;
+  static constexpr int RB = N / R;                   // row blocks per frame
   static constexpr int TILES = H / 8;                // 8-column tiles of the intermediate
 };
 
@@ -58,238 +60,350 @@ struct ColCfg {
   static constexpr int TILES = N / 16;
 };
 
+// Frames one workgroup of a pass loops over: enough workgroups to give
+// every CU two, and at most 8 frames each.
+inline int frames_per_group(int nframes, int groups_per_frame) {
+  int f = (nframes * groups_per_frame) / 512;
+  if (f < 1) f = 1;
+  if (f > 8) f = 8;
+  return f;
+}
+
+template <typename T>
+struct RawPair;  // two neighbouring pixels as loaded
+template <>
+struct RawPair<uint16_t> {
+  using type = uint32_t;
+};
+template <>
+struct RawPair<float> {
+  using type = float2;
+};
+
+template <typename T>
+__device__ __forceinline__ typename RawPair<T>::type load_pair(const T* p) {
+  return *reinterpret_cast<const typename RawPair<T>::type*>(p);
+}
+
 // ---------------------------------------------------------------------------
-// Row pass. Real row u of N pixels -> z[j] = u[2j] + i u[2j+1] (H points),
-// Z = DFT_H(z), then X[k] = (Z[k] + conj Z[H-k])/2 - i W_N^k (Z[k] - conj Z[H-k])/2
-// for k = 0..H-1 (the real-input split; X[H] is never binned).
+// Row pass. Real row u of N pixels (minus the reference row, times the
+// window) -> z[j] = u[2j] + i u[2j+1] (H points), Z = DFT_H(z), then
+// X[k] = (Z[k] + conj Z[H-k])/2 - i W_N^k (Z[k] - conj Z[H-k])/2 for
+// k = 0..H-1 (the real-input split; X[H] is never binned). A workgroup owns
+// R rows and loops over up to `per_group` frames of the batch, loading the
+// next frame's pixels while it transforms the current one.
 template <int N, typename T, bool WIN>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
     const T* __restrict__ frames, const T* __restrict__ ref, const float* __restrict__ window,
-    int64_t total_rows, float2* __restrict__ inter, double* __restrict__ rowsum,
+    int nframes, int per_group, float2* __restrict__ inter, double* __restrict__ rowsum,
     const float2* __restrict__ tw) {
   using C = RowCfg<N>;
-  constexpr int H = C::H, P1 = C::P1, P2 = C::P2, Q = C::Q, R = C::R;
+  using Raw = typename RawPair<T>::type;
+  constexpr bool U16 = std::is_same<T, uint16_t>::value;
+  constexpr int H = C::H, P1 = C::P1, P2 = C::P2, Q = C::Q, R = C::R, RB = C::RB;
   constexpr int PITCH = C::PITCH, THREADS = C::THREADS, TILES = C::TILES;
   __shared__ float2 lds[R * PITCH];
+  __shared__ float2 twl[N];
 
   const int tid = threadIdx.x;
   const int rl = tid / P1, j1 = tid % P1;
-  const int64_t g0 = int64_t(blockIdx.x) * R;
-  const int64_t grow = g0 + rl;
-  const bool valid = grow < total_rows;
-  const int y = int(grow & (N - 1));
+  const int rblk = blockIdx.x % RB;
+  const int f_begin = (blockIdx.x / RB) * per_group;
+  const int f_end = min(nframes, f_begin + per_group);
+  const int y0 = rblk * R;
+  const int y = y0 + rl;
   float2* row_lds = lds + rl * PITCH;
 
-  float2 v[P2];
-  double s = 0.0;
-  const T* src = frames + grow * N;
+  for (int i = tid; i < N; i += THREADS) twl[i] = tw[i];
+
+  // Up to 32 pixel pairs per thread the reference row stays in registers and
+  // the next frame is prefetched; larger rows reload both from cache.
+  constexpr bool CACHE = P2 <= 32;
+  constexpr int NC = CACHE ? P2 : 1;
+  Raw refv[NC], raw[NC];
+  auto ref_pair = [&](int j2) -> Raw {
+    if (!ref) {
+      if constexpr (U16) return 0u; else return make_float2(0.f, 0.f);
+    }
+    return load_pair(ref + int64_t(y) * N + 2 * (j1 + P1 * j2));
+  };
+  auto raw_pair = [&](int f, int j2) -> Raw {
+    return load_pair(frames + (int64_t(f) * N + y) * N + 2 * (j1 + P1 * j2));
+  };
+  auto load_raw = [&](int f) {
 #pragma unroll
-  for (int j2 = 0; j2 < P2; ++j2) {
-    const int j = j1 + P1 * j2;
-    float a = 0.f, b = 0.f;
-    if (valid) {
-      if constexpr (std::is_same<T, uint16_t>::value) {
-        const uint32_t w = *reinterpret_cast<const uint32_t*>(src + 2 * j);
-        a = float(w & 0xffffu);
-        b = float(w >> 16);
-        if (ref) {  // integer difference: exact in FP32
-          const uint32_t r = *reinterpret_cast<const uint32_t*>(ref + int64_t(y) * N + 2 * j);
-          a -= float(r & 0xffffu);
-          b -= float(r >> 16);
-        }
+    for (int j2 = 0; j2 < NC; ++j2) raw[j2] = raw_pair(f, j2);
+  };
+  if constexpr (CACHE) {
+#pragma unroll
+    for (int j2 = 0; j2 < P2; ++j2) refv[j2] = ref_pair(j2);
+    if (f_begin < f_end) load_raw(f_begin);
+  }
+  __syncthreads();
+
+  for (int f = f_begin; f < f_end; ++f) {
+    float2 v[P2];
+    int si = 0;
+    double sd = 0.0;
+#pragma unroll
+    for (int j2 = 0; j2 < P2; ++j2) {
+      float a, b;
+      Raw rp, px;
+      if constexpr (CACHE) {
+        rp = refv[j2];
+        px = raw[j2];
       } else {
-        const float2 w = *reinterpret_cast<const float2*>(src + 2 * j);
-        a = w.x;
-        b = w.y;
-        if (ref) {
-          const float2 r = *reinterpret_cast<const float2*>(ref + int64_t(y) * N + 2 * j);
-          a -= r.x;
-          b -= r.y;
-        }
+        rp = ref_pair(j2);
+        px = raw_pair(f, j2);
+      }
+      if constexpr (U16) {
+        // Integer difference from the reference: exact, and summed exactly.
+        const int da = int(px & 0xffffu) - int(rp & 0xffffu);
+        const int db = int(px >> 16) - int(rp >> 16);
+        a = float(da);
+        b = float(db);
+        if constexpr (!WIN) si += da + db;
+      } else {
+        a = px.x - rp.x;
+        b = px.y - rp.y;
       }
       if constexpr (WIN) {
-        const float2 ww = *reinterpret_cast<const float2*>(window + int64_t(y) * N + 2 * j);
+        const float2 ww =
+            *reinterpret_cast<const float2*>(window + int64_t(y) * N + 2 * (j1 + P1 * j2));
         a *= ww.x;
         b *= ww.y;
       }
+      if constexpr (!U16 || WIN) sd += double(a) + double(b);
+      v[j2] = make_float2(a, b);
     }
-    v[j2] = make_float2(a, b);
-    s += double(a) + double(b);
-  }
-  // Row sum of what was transformed (exact in double for integer pixels),
-  // butterfly over the P1 lanes of the row: every lane ends with the same
-  // value.
+    // Next frame's pixels are in flight while this one is transformed.
+    if constexpr (CACHE) {
+      if (f + 1 < f_end) load_raw(f + 1);
+    }
+    // Row sum of what is transformed, butterfly over the row's P1 lanes.
+    double s;
+    if constexpr (U16 && !WIN) {
 #pragma unroll
-  for (int o = P1 / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, P1);
-  if (valid && j1 == 0) rowsum[grow] = s;
-
-  // First level: DFT over j2 of z[j1 + P1 j2], twiddle W_H^{j1 k2} = W_N^{2 j1 k2}.
-  dft<P2>(v);
-  static_for<P2>([&](auto K2) {
-    constexpr int k2 = decltype(K2)::value;
-    float2 yv = v[bitrev<P2>(k2)];
-    if constexpr (k2 != 0) yv = cmul(yv, tw[(2 * j1 * k2) & (N - 1)]);
-    row_lds[k2 * (P1 + 1) + j1] = yv;
-  });
-  __syncthreads();
-
-  // Second level: for k2 = j1 + q P1, DFT over j1 gives Z[k2 + P2 k1].
-  float2 z[Q][P1];
-  static_for<Q>([&](auto QQ) {
-    constexpr int q = decltype(QQ)::value;
-    const int k2 = j1 + q * P1;
-    float2 w[P1];
+      for (int o = P1 / 2; o >= 1; o >>= 1) si += __shfl_xor(si, o, P1);
+      s = double(si);
+    } else {
 #pragma unroll
-    for (int j = 0; j < P1; ++j) w[j] = row_lds[k2 * (P1 + 1) + j];
-    dft<P1>(w);
-    static_for<P1>([&](auto K1) {
-      constexpr int k1 = decltype(K1)::value;
-      z[q][k1] = w[bitrev<P1>(k1)];
+      for (int o = P1 / 2; o >= 1; o >>= 1) sd += __shfl_xor(sd, o, P1);
+      s = sd;
+    }
+    if (j1 == 0) rowsum[int64_t(f) * N + y] = s;
+
+    // First level: DFT over j2 of z[j1 + P1 j2], twiddle W_H^{j1 k2} = W_N^{2 j1 k2}.
+    dft<P2>(v);
+    static_for<P2>([&](auto K2) {
+      constexpr int k2 = decltype(K2)::value;
+      float2 yv = v[bitrev<P2>(k2)];
+      if constexpr (k2 != 0) yv = cmul(yv, twl[(2 * j1 * k2) & (N - 1)]);
+      row_lds[k2 * (P1 + 1) + j1] = yv;
     });
-  });
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < Q; ++q)
-#pragma unroll
-    for (int k1 = 0; k1 < P1; ++k1) row_lds[(j1 + q * P1) + P2 * k1] = z[q][k1];
-  __syncthreads();
+    __syncthreads();
 
-  // Real-input split and store into 8-column tiles: for tile T the rows of
-  // this workgroup are contiguous in the intermediate.
+    // Second level: for k2 = j1 + q P1, DFT over j1 gives Z[k2 + P2 k1].
+    float2 z[Q][P1];
+    static_for<Q>([&](auto QQ) {
+      constexpr int q = decltype(QQ)::value;
+      const int k2 = j1 + q * P1;
+      float2 w[P1];
 #pragma unroll
-  for (int i = 0; i < P2; ++i) {
-    const int idx = tid + i * THREADS;
-    const int c = idx & 7;
-    const int rr = (idx >> 3) & (R - 1);
-    const int tile = idx / (8 * R);
-    const int k = tile * 8 + c;
-    const int64_t g = g0 + rr;
-    if (g < total_rows) {
+      for (int j = 0; j < P1; ++j) w[j] = row_lds[k2 * (P1 + 1) + j];
+      dft<P1>(w);
+      static_for<P1>([&](auto K1) {
+        constexpr int k1 = decltype(K1)::value;
+        z[q][k1] = w[bitrev<P1>(k1)];
+      });
+    });
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int k1 = 0; k1 < P1; ++k1) row_lds[(j1 + q * P1) + P2 * k1] = z[q][k1];
+    __syncthreads();
+
+    // Real-input split and store into 8-column tiles: for a tile the rows of
+    // this workgroup are contiguous in the intermediate.
+    float2* dst = inter + (int64_t(f) * TILES * N + y0) * 8;
+#pragma unroll
+    for (int i = 0; i < P2; ++i) {
+      const int idx = tid + i * THREADS;
+      const int c = idx & 7;
+      const int rr = (idx >> 3) & (R - 1);
+      const int tile = idx / (8 * R);
+      const int k = tile * 8 + c;
       const float2 zk = lds[rr * PITCH + k];
       const float2 zm = lds[rr * PITCH + ((H - k) & (H - 1))];
       const float2 e = make_float2(zk.x + zm.x, zk.y - zm.y);   // Z[k] + conj Z[H-k]
       const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);   // Z[k] - conj Z[H-k]
-      const float2 wd = cmul(d, tw[k]);
-      const float2 X = make_float2(0.5f * (e.x + wd.y), 0.5f * (e.y - wd.x));
-      const int64_t f = g / N;
-      const int yy = int(g & (N - 1));
-      inter[((f * TILES + tile) * N + yy) * 8 + c] = X;
+      const float2 wd = cmul(d, twl[k]);
+      dst[(int64_t(tile) * N + rr) * 8 + c] =
+          make_float2(0.5f * (e.x + wd.y), 0.5f * (e.y - wd.x));
+    }
+    __syncthreads();  // LDS is rewritten by the next frame
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Frame scales from the row sums, in a fixed order (strided partial sums,
+// butterfly per wave, waves in index order). REF: the rows were the
+// reference image; refscal = {S_ref, n^2/S_ref}. Otherwise the rows were
+// (image - reference): S = S_ref + sum, sigma = n^2/S and
+// fscale[f] = {sigma, sigma - sigma_ref}; a frame whose S is not positive
+// and finite gets sigma = 0 and sets bit 0 of *status.
+template <bool REF>
+__global__ __launch_bounds__(256) void frame_scale_kernel(int n, const double* __restrict__ rowsum,
+                                                          double* __restrict__ refscal,
+                                                          float2* __restrict__ fscale,
+                                                          int32_t* __restrict__ status) {
+  __shared__ double red[4];
+  const int f = blockIdx.x, tid = threadIdx.x;
+  double s = 0.0;
+  for (int y = tid; y < n; y += 256) s += rowsum[int64_t(f) * n + y];
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) {
+    const double part = ((red[0] + red[1]) + red[2]) + red[3];
+    const double total = REF ? part : refscal[0] + part;
+    const bool bad = !(total > 0.0) || !isfinite(total);
+    const double sigma = bad ? 0.0 : double(n) * double(n) / total;
+    if constexpr (REF) {
+      refscal[0] = total;
+      refscal[1] = sigma;
+    } else {
+      fscale[f] = make_float2(float(sigma), float(sigma - refscal[1]));
+      if (bad) atomicOr(status, 1);
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// Column pass over CW columns of one frame: DFT_N over the rows, scale by
-// n^2 / sum(u) (the zero-frequency value of the row-pass output), set
-// I(0) = n^2 exactly and store the modes with k_x < row_width[r].
+// Column pass over CW columns: DFT_N over the rows of each frame of the
+// group. REF: store the reference transform unscaled in refspec. Otherwise
+// store sigma * X + (sigma - sigma_ref) * refspec (= I_t - sigma_ref *
+// F[reference], fluctuation-sized) with I_t(0) - sigma_ref F[ref](0) := 0,
+// at the stored modes (k_x < row_width[r]) of ring slot (t0 + f) mod
+// capacity. Per-thread store addresses and reference values are loaded
+// once; the next frame's columns are loaded during the second level.
 template <int N, bool REF>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
-    const float2* __restrict__ inter, const double* __restrict__ rowsum, int64_t t0,
-    int64_t capacity, int64_t mode_stride, const int32_t* __restrict__ row_width,
-    const int32_t* __restrict__ row_offset, const float2* __restrict__ tw,
-    float2* __restrict__ ring, float2* __restrict__ refspec, double* __restrict__ refscal,
-    int32_t* __restrict__ status) {
+    const float2* __restrict__ inter, const float2* __restrict__ fscale, int nframes,
+    int per_group, int64_t t0, int64_t capacity, int64_t mode_stride,
+    const int32_t* __restrict__ row_width, const int32_t* __restrict__ row_offset,
+    const float2* __restrict__ tw, float2* __restrict__ ring, float2* __restrict__ refspec) {
   using C = ColCfg<N>;
   constexpr int P1 = C::P1, P2 = C::P2, Q = C::Q, CP = C::CP, CW = C::CW;
   constexpr int THREADS = C::THREADS, GROUPS = C::GROUPS, TILES = C::TILES;
-  constexpr int WAVE = THREADS < 64 ? THREADS : 64;
-  constexpr int NWAVES = (THREADS + 63) / 64;
   __shared__ float2 lds[CW * CP];
-  __shared__ double red[NWAVES];
+  __shared__ float2 twl[N];
 
-  const int f = blockIdx.x / GROUPS;
   const int grp = blockIdx.x % GROUPS;
+  const int f_begin = (blockIdx.x / GROUPS) * per_group;
+  const int f_end = min(nframes, f_begin + per_group);
   const int kx0 = grp * CW;
   const int tile = kx0 / 8, c0 = kx0 % 8;
   const int tid = threadIdx.x;
   const int c = tid % CW, j1 = tid / CW;
+  const int kx = kx0 + c;
 
-  // Frame sum in a fixed order: strided partial sums, butterfly within the
-  // wave, waves added in index order. Every workgroup of the frame gets the
-  // same value.
-  double s = 0.0;
-  for (int yy = tid; yy < N; yy += THREADS) s += rowsum[int64_t(f) * N + yy];
+  for (int i = tid; i < N; i += THREADS) twl[i] = tw[i];
+
+  // Outputs of this thread: rows r = (j1 + q P1) + P2 k1 of column kx. Up
+  // to 32 outputs per thread their store index and reference value stay in
+  // registers across frames; more are looked up again per frame.
+  constexpr bool CACHE = Q * P1 <= 32;
+  constexpr int QC = CACHE ? Q : 1, PC = CACHE ? P1 : 1;
+  auto store_index = [&](int q, int k1) {
+    const int r = (j1 + q * P1) + P2 * k1;
+    return kx < row_width[r] ? row_offset[r] + kx : -1;
+  };
+  int at[QC][PC];
+  float2 rv[QC][PC];
+  if constexpr (CACHE) {
 #pragma unroll
-  for (int o = WAVE / 2; o >= 1; o >>= 1) s += __shfl_xor(s, o, WAVE);
-  if ((tid & 63) == 0) red[tid >> 6] = s;
-  __syncthreads();
-  double part = 0.0;
+    for (int q = 0; q < Q; ++q)
 #pragma unroll
-  for (int w = 0; w < NWAVES; ++w) part += red[w];
-  // REF: the rows were the reference image itself; its transform is stored
-  // unscaled in refspec and its sum S_ref and scale n^2/S_ref in refscal.
-  // Otherwise the rows were (image - reference): the image sum is
-  // S_ref + part, sigma = n^2 / sum, and the stored value is
-  // sigma * F[image - reference] + (sigma - sigma_ref) * F[reference]
-  // = I_t - sigma_ref * F[reference], fluctuation-sized.
-  const double total = REF ? part : refscal[0] + part;
-  const bool bad = !(total > 0.0) || !isfinite(total);
-  const double sigma = bad ? 0.0 : double(N) * double(N) / total;
-  float scale, dscale;
-  if constexpr (REF) {
-    scale = 1.f;
-    dscale = 0.f;
-    if (blockIdx.x == 0 && tid == 0) {
-      refscal[0] = total;
-      refscal[1] = sigma;
-    }
-  } else {
-    scale = float(sigma);
-    dscale = float(sigma - refscal[1]);
-    if (bad && tid == 0) atomicOr(status, 1);
+      for (int k1 = 0; k1 < P1; ++k1) {
+        at[q][k1] = store_index(q, k1);
+        rv[q][k1] = make_float2(0.f, 0.f);
+        if constexpr (!REF) {
+          if (at[q][k1] >= 0) rv[q][k1] = refspec[at[q][k1]];
+        }
+      }
   }
 
-  const float2* src = inter + (int64_t(f) * TILES + tile) * N * 8 + c0 + c;
-  float2 v[P2];
+  auto load_cols = [&](float2 (&v)[P2], int f) {
+    const float2* src = inter + (int64_t(f) * TILES + tile) * N * 8 + c0 + c;
 #pragma unroll
-  for (int j2 = 0; j2 < P2; ++j2) v[j2] = src[(j1 + P1 * j2) * 8];
-  dft<P2>(v);
+    for (int j2 = 0; j2 < P2; ++j2) v[j2] = src[(j1 + P1 * j2) * 8];
+  };
+  float2 v[P2];
+  if (CACHE && f_begin < f_end) load_cols(v, f_begin);
   float2* col_lds = lds + c * CP;
-  static_for<P2>([&](auto K2) {
-    constexpr int k2 = decltype(K2)::value;
-    float2 yv = v[bitrev<P2>(k2)];
-    if constexpr (k2 != 0) yv = cmul(yv, tw[(j1 * k2) & (N - 1)]);
-    col_lds[k2 * (P1 + 1) + j1] = yv;
-  });
   __syncthreads();
 
-  float2* dst = REF ? refspec : ring + ((t0 + f) % capacity) * mode_stride;
-  const int kx = kx0 + c;
-  static_for<Q>([&](auto QQ) {
-    constexpr int q = decltype(QQ)::value;
-    const int k2 = j1 + q * P1;
-    float2 w[P1];
-#pragma unroll
-    for (int j = 0; j < P1; ++j) w[j] = col_lds[k2 * (P1 + 1) + j];
-    dft<P1>(w);
-    static_for<P1>([&](auto K1) {
-      constexpr int k1 = decltype(K1)::value;
-      const int r = k2 + P2 * k1;
-      float2 X = w[bitrev<P1>(k1)];
-      if (kx < row_width[r]) {
-        const int64_t at = row_offset[r] + kx;
-        if constexpr (!REF) {
-          const float2 R = refspec[at];
-          X.x = fmaf(dscale, R.x, scale * X.x);
-          X.y = fmaf(dscale, R.y, scale * X.y);
-          // I_t(0) = n^2 for every frame, so its offset from the reference is 0.
-          if (at == 0) X = make_float2(0.f, 0.f);
-        }
-        dst[at] = X;
-      }
+  for (int f = f_begin; f < f_end; ++f) {
+    if constexpr (!CACHE) load_cols(v, f);
+    dft<P2>(v);
+    static_for<P2>([&](auto K2) {
+      constexpr int k2 = decltype(K2)::value;
+      float2 yv = v[bitrev<P2>(k2)];
+      if constexpr (k2 != 0) yv = cmul(yv, twl[(j1 * k2) & (N - 1)]);
+      col_lds[k2 * (P1 + 1) + j1] = yv;
     });
-  });
+    __syncthreads();
+    if constexpr (CACHE) {
+      if (f + 1 < f_end) load_cols(v, f + 1);
+    }
+
+    float scale = 1.f, dscale = 0.f;
+    if constexpr (!REF) {
+      const float2 sc = fscale[f];
+      scale = sc.x;
+      dscale = sc.y;
+    }
+    float2* dst = REF ? refspec : ring + ((t0 + f) % capacity) * mode_stride;
+    static_for<Q>([&](auto QQ) {
+      constexpr int q = decltype(QQ)::value;
+      const int k2 = j1 + q * P1;
+      float2 w[P1];
+#pragma unroll
+      for (int j = 0; j < P1; ++j) w[j] = col_lds[k2 * (P1 + 1) + j];
+      dft<P1>(w);
+      static_for<P1>([&](auto K1) {
+        constexpr int k1 = decltype(K1)::value;
+        int a;
+        if constexpr (CACHE) a = at[q][k1]; else a = store_index(q, k1);
+        if (a >= 0) {
+          float2 X = w[bitrev<P1>(k1)];
+          if constexpr (!REF) {
+            float2 Rv;
+            if constexpr (CACHE) Rv = rv[q][k1]; else Rv = refspec[a];
+            X.x = fmaf(dscale, Rv.x, scale * X.x);
+            X.y = fmaf(dscale, Rv.y, scale * X.y);
+            if (a == 0) X = make_float2(0.f, 0.f);
+          }
+          dst[a] = X;
+        }
+      });
+    });
+    __syncthreads();  // LDS is rewritten by the next frame
+  }
 }
 
 template <int N, typename T, bool WIN>
 hipError_t row_launch(const void* frames, const void* ref, const float* window, int nframes,
                       float2* inter, double* rowsum, const float2* tw, hipStream_t s) {
   using C = RowCfg<N>;
-  const int64_t rows = int64_t(nframes) * N;
-  const int64_t blocks = (rows + C::R - 1) / C::R;
+  const int per = frames_per_group(nframes, C::RB);
+  const int64_t blocks = int64_t(C::RB) * ((nframes + per - 1) / per);
   hipLaunchKernelGGL((row_pass_kernel<N, T, WIN>), dim3(unsigned(blocks)), dim3(C::THREADS),
                      0, s, static_cast<const T*>(frames), static_cast<const T*>(ref), window,
-                     rows, inter, rowsum, tw);
+                     nframes, per, inter, rowsum, tw);
   return hipGetLastError();
 }
 
@@ -311,18 +425,23 @@ template <int N>
 hipError_t col_launch(bool reference, const float2* inter, const double* rowsum, int nframes,
                       int64_t t0, int64_t capacity, int64_t mode_stride,
                       const int32_t* row_width, const int32_t* row_offset, const float2* tw,
-                      float2* ring, float2* refspec, double* refscal, int32_t* status,
-                      hipStream_t s) {
+                      float2* ring, float2* refspec, double* refscal, float2* fscale,
+                      int32_t* status, hipStream_t s) {
   using C = ColCfg<N>;
-  const int64_t blocks = int64_t(nframes) * C::GROUPS;
+  const int per = frames_per_group(nframes, C::GROUPS);
+  const int64_t blocks = int64_t(C::GROUPS) * ((nframes + per - 1) / per);
   if (reference) {
+    hipLaunchKernelGGL(frame_scale_kernel<true>, dim3(unsigned(nframes)), dim3(256), 0, s, N,
+                       rowsum, refscal, fscale, status);
     hipLaunchKernelGGL((col_pass_kernel<N, true>), dim3(unsigned(blocks)), dim3(C::THREADS), 0,
-                       s, inter, rowsum, t0, capacity, mode_stride, row_width, row_offset, tw,
-                       ring, refspec, refscal, status);
+                       s, inter, fscale, nframes, per, t0, capacity, mode_stride, row_width,
+                       row_offset, tw, ring, refspec);
   } else {
+    hipLaunchKernelGGL(frame_scale_kernel<false>, dim3(unsigned(nframes)), dim3(256), 0, s, N,
+                       rowsum, refscal, fscale, status);
     hipLaunchKernelGGL((col_pass_kernel<N, false>), dim3(unsigned(blocks)), dim3(C::THREADS), 0,
-                       s, inter, rowsum, t0, capacity, mode_stride, row_width, row_offset, tw,
-                       ring, refspec, refscal, status);
+                       s, inter, fscale, nframes, per, t0, capacity, mode_stride, row_width,
+                       row_offset, tw, ring, refspec);
   }
   return hipGetLastError();
 }
@@ -354,11 +473,12 @@ hipError_t launch_col_pass(int n, bool reference, const float2* inter, const dou
                            int nframes, int64_t t0, int64_t capacity, int64_t mode_stride,
                            const int32_t* row_width, const int32_t* row_offset,
                            const float2* tw, float2* ring, float2* refspec, double* refscal,
-                           int32_t* status, hipStream_t s) {
+                           float2* fscale, int32_t* status, hipStream_t s) {
 #define NFS_COL_CASE(NN)                                                                   \
   case NN:                                                                                 \
     return col_launch<NN>(reference, inter, rowsum, nframes, t0, capacity, mode_stride,   \
-                          row_width, row_offset, tw, ring, refspec, refscal, status, s);
+                          row_width, row_offset, tw, ring, refspec, refscal, fscale, status, \
+                          s);
   switch (n) {
     NFS_COL_CASE(16)
     NFS_COL_CASE(32)

@@ -33,6 +33,7 @@ struct nfs_plan_s {
   double* refscal = nullptr;    // {S_ref, sigma_ref} of the reference frame
   void* ref = nullptr;          // reference frame: first frame of the sequence
   float2* refspec = nullptr;    // its transform on the stored modes
+  float2* fscale = nullptr;     // per-frame scales of the current batch
   float2* tw = nullptr;
   int32_t* width = nullptr;
   int32_t* offset = nullptr;
@@ -151,6 +152,7 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->refscal = reinterpret_cast<double*>(h->ws + L.off_status + 8);
   h->ref = h->ws + L.off_ref;
   h->refspec = reinterpret_cast<float2*>(h->ws + L.off_refspec);
+  h->fscale = reinterpret_cast<float2*>(h->ws + L.off_fscale);
 
   const std::vector<float> tw = nfs::twiddle_table(L.n);
   hipError_t e = hipMemcpyAsync(h->tw, tw.data(), tw.size() * sizeof(float),
@@ -218,7 +220,7 @@ nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count) {
       if (e == hipSuccess)
         e = nfs::launch_col_pass(L.n, true, h->inter, h->rowsum, 1, 0, L.capacity,
                                  L.mode_stride, h->width, h->offset, h->tw, h->ring,
-                                 h->refspec, h->refscal, h->status, h->stream);
+                                 h->refspec, h->refscal, h->fscale, h->status, h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "reference transform launch");
     }
     e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->ref, h->window, int(b), h->inter,
@@ -226,7 +228,7 @@ nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count) {
     if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
     e = nfs::launch_col_pass(L.n, false, h->inter, h->rowsum, int(b), h->t_pushed, L.capacity,
                              L.mode_stride, h->width, h->offset, h->tw, h->ring, h->refspec,
-                             h->refscal, h->status, h->stream);
+                             h->refscal, h->fscale, h->status, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
     h->t_pushed += b;
     i += b;

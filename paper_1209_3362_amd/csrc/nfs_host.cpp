@@ -71,8 +71,9 @@ static bool plan_group(const std::vector<int32_t>& lags, int first, int count,
   g->max_lag = lags[first + count - 1];
   g->modes = 0;
   for (int K : {64, 32, 16, 8}) {
-    const int H = int(align_up(size_t(g->max_lag + 2 * kPairChunk), kPairChunk));
-    const size_t lds = size_t(H + kPairChunk) * K * 8;
+    const int S = pair_chunk(K);
+    const int H = int(align_up(size_t(g->max_lag + 2 * S), S));
+    const size_t lds = size_t(H + S) * K * 8;
     if (lds <= size_t(kLdsBytes)) {
       g->modes = K;
       g->hist = H;
@@ -160,6 +161,7 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_lags = take(size_t(o.n_lags) * 4);
   o.off_ref = take(size_t(o.n) * o.n * (o.in_dtype == NFS_IN_U16 ? 2 : 4));
   o.off_refspec = take(size_t(o.mode_stride) * 8);
+  o.off_fscale = take(size_t(o.batch) * 8);
   o.off_ring = off;
   const size_t spec_bytes = size_t(o.mode_stride) * 8;
 

@@ -15,12 +15,13 @@ namespace nfs {
 constexpr int kMinN = 16;
 constexpr int kMaxN = 4096;
 constexpr size_t kAlign = 256;
-// Rows of the time series handled per step of the pair kernel.
-constexpr int kPairChunk = 32;
+// Frames of the time series handled per step of the pair kernel with K
+// modes per workgroup (every lane then holds at most 16 target frames).
+constexpr int pair_chunk(int K) { return K == 64 ? 16 : 32; }
 // Most lags one wave of the pair kernel accumulates at once, and most waves
 // per workgroup; a launch handles at most their product.
 constexpr int kMaxLagsPerWave = 8;
-constexpr int kMaxPairWaves = 16;
+constexpr int kMaxPairWaves = 8;
 // LDS a workgroup may allocate on gfx950.
 constexpr int kLdsBytes = 160 * 1024;
 // Largest delay the pair kernel's on-chip history supports (K = 8 modes).
@@ -48,7 +49,7 @@ struct LagGroup {
   int count = 0;      // lags in the group
   int max_lag = 0;    // largest lag of the group
   int modes = 0;      // K: modes per workgroup
-  int hist = 0;       // H: history rows kept in LDS (multiple of kPairChunk)
+  int hist = 0;       // H: history rows kept in LDS (multiple of the chunk)
   int waves = 0;      // waves per workgroup
   int per_wave = 0;   // lags per wave (<= kMaxLagsPerWave)
   size_t lds = 0;     // dynamic LDS bytes
@@ -70,6 +71,7 @@ struct Layout {
   size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_acc = 0;
   size_t off_status = 0, off_tw = 0, off_width = 0, off_offset = 0;
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
+  size_t off_fscale = 0;                // per-frame {sigma, sigma - sigma_ref}
   size_t off_lags = 0, total = 0;
 };
 

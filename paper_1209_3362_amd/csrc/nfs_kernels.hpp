@@ -18,19 +18,20 @@ hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* 
                            const float* window, int nframes, float2* inter, double* rowsum,
                            const float2* tw, hipStream_t s);
 
-// Column pass (per column k_x: complex transform over the n rows).
+// Frame scales from the row sums, then the column pass (per column k_x:
+// complex transform over the n rows).
 // reference == true: the rows are the reference image (one frame); store its
 // transform unscaled in refspec and refscal = {S_ref, n^2/S_ref}.
 // reference == false: the rows are (frame - reference); with
-// sigma = n^2 / (S_ref + row sums) store
-// sigma * X + (sigma - sigma_ref) * refspec, 0 at k = 0, for frame f into
-// ring slot (t0 + f) mod capacity. A frame whose sum is not positive and
-// finite sets bit 0 of *status and gets sigma = 0.
+// sigma = n^2 / (S_ref + row sums), fscale[f] = {sigma, sigma - sigma_ref},
+// store sigma * X + (sigma - sigma_ref) * refspec, 0 at k = 0, for frame f
+// into ring slot (t0 + f) mod capacity. A frame whose sum is not positive
+// and finite sets bit 0 of *status and gets sigma = 0.
 hipError_t launch_col_pass(int n, bool reference, const float2* inter, const double* rowsum,
                            int nframes, int64_t t0, int64_t capacity, int64_t mode_stride,
                            const int32_t* row_width, const int32_t* row_offset,
                            const float2* tw, float2* ring, float2* refspec, double* refscal,
-                           int32_t* status, hipStream_t s);
+                           float2* fscale, int32_t* status, hipStream_t s);
 
 // Lag-pair accumulation for target frames [T0, T1) and the lags
 // lags[0..n_lags): acc[l][m] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2 over

@@ -19,16 +19,16 @@
 namespace nfs {
 namespace {
 
-constexpr int S = kPairChunk;
 constexpr int MAXLW = kMaxLagsPerWave;
 
 template <int K>
-__global__ __launch_bounds__(1024) void pair_kernel(
+__global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
     const float2* __restrict__ ring, int64_t n_modes, int64_t mode_stride, int64_t capacity,
     int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags, int max_lag,
     float* __restrict__ acc, int H, int per_wave) {
-  constexpr int G = 64 / K;       // lanes sharing one mode inside a wave
-  constexpr int RPT = S / G;      // target rows per lane per chunk
+  constexpr int S = pair_chunk(K); // frames per chunk
+  constexpr int G = 64 / K;         // lanes sharing one mode inside a wave
+  constexpr int RPT = S / G;        // target rows per lane per chunk
   constexpr int V4 = K / 2;       // float4 (two modes) per ring row of the tile
   // float4 per thread per chunk; launches have at least 4 waves.
   constexpr int MAXPF = (S * V4 / 256) > 0 ? (S * V4 / 256) : 1;
@@ -37,18 +37,27 @@ __global__ __launch_bounds__(1024) void pair_kernel(
 
   const int nthreads = blockDim.x;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int m = lane % K, g = lane / K;
   const int64_t m0 = int64_t(blockIdx.x) * K;
+  const int len = int(T1 - T0);  // frames in this window (< capacity)
 
+  // This wave's lags, wave-uniform (scalar registers). A target frame at
+  // window offset u has a partner for lag tau iff u >= first[s].
   const int l_begin = wave * per_wave;
   const int l_count = max(0, min(per_wave, n_lags - l_begin));
-  int tau[MAXLW];
+  int tau[MAXLW], first[MAXLW];
+  int first_max = 0;
 #pragma unroll
-  for (int s = 0; s < MAXLW; ++s) tau[s] = s < l_count ? lags[l_begin + s] : 0;
+  for (int s = 0; s < MAXLW; ++s) {
+    const int ts = s < l_count ? lags[l_begin + s] : 0;
+    tau[s] = __builtin_amdgcn_readfirstlane(ts);
+    const int64_t f = int64_t(ts) - T0;
+    first[s] = __builtin_amdgcn_readfirstlane(int(f > 0 ? f : 0));
+    first_max = max(first_max, first[s]);
+  }
 
-  // Time t lives in LDS row (t - Tb) mod H, Tb = T0 - max_lag.
-  const int64_t Tb = T0 - max_lag;
+  // Window offset u lives in LDS row (u + max_lag) mod H.
   auto slot_row = [&](int64_t slot) -> const float4* {
     return reinterpret_cast<const float4*>(ring + slot * mode_stride + m0);
   };
@@ -59,26 +68,26 @@ __global__ __launch_bounds__(1024) void pair_kernel(
 
   // History from earlier windows: frames [max(0, T0 - max_lag), T0).
   {
-    const int64_t r0 = T0 - max_lag > 0 ? T0 - max_lag : 0;
-    const int64_t nrows = T0 - r0;
-    for (int64_t e = threadIdx.x; e < nrows * V4; e += nthreads) {
-      const int64_t t = r0 + e / V4;
-      const int col2 = int(e % V4);
-      put_row(int((t - Tb) % H), col2, slot_row(t % capacity)[col2]);
+    const int pre = int(T0 - max_lag > 0 ? max_lag : T0);
+    int64_t slot = (T0 - pre) % capacity;
+    for (int r = 0; r < pre; ++r) {
+      for (int col2 = threadIdx.x; col2 < V4; col2 += nthreads)
+        put_row((max_lag - pre + r) % H, col2, slot_row(slot)[col2]);
+      if (++slot == capacity) slot = 0;
     }
   }
 
   float4 pf[MAXPF];
   const int n_el = S * V4;  // float4 per chunk
-  // Chunk c's first frame is in ring slot cslot; slots of the chunk wrap once.
-  auto prefetch = [&](int64_t c, int64_t cslot) {
+  // Chunk at window offset c starts in ring slot cslot; slots wrap once.
+  auto prefetch = [&](int c, int64_t cslot) {
 #pragma unroll
     for (int i = 0; i < MAXPF; ++i) {
       const int e = threadIdx.x + i * nthreads;
       pf[i] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (e < n_el) {
         const int dt = e / V4;
-        if (c + dt < T1) {
+        if (c + dt < len) {
           int64_t slot = cslot + dt;
           if (slot >= capacity) slot -= capacity;
           pf[i] = slot_row(slot)[e % V4];
@@ -86,7 +95,7 @@ __global__ __launch_bounds__(1024) void pair_kernel(
       }
     }
   };
-  auto commit = [&](int64_t c, int crow) {
+  auto commit = [&](int crow) {
 #pragma unroll
     for (int i = 0; i < MAXPF; ++i) {
       const int e = threadIdx.x + i * nthreads;
@@ -102,45 +111,71 @@ __global__ __launch_bounds__(1024) void pair_kernel(
 #pragma unroll
   for (int s = 0; s < MAXLW; ++s) ax[s] = ay[s] = 0.f;
 
-  int crow = int((T0 - Tb) % H);  // LDS row of the chunk's first frame
+  auto accumulate = [&](const float2 (&cur)[RPT], const float2 (&old)[RPT], int s) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const float dx = cur[i].x - old[i].x, dy = cur[i].y - old[i].y;
+      ax[s] = fmaf(dx, dx, ax[s]);
+      ay[s] = fmaf(dy, dy, ay[s]);
+    }
+  };
+
+  int crow = max_lag % H;         // LDS row of the chunk's first frame
   int64_t cslot = T0 % capacity;  // ring slot of the chunk's first frame
-  prefetch(T0, cslot);
-  for (int64_t c = T0; c < T1; c += S) {
-    commit(c, crow);
+  prefetch(0, cslot);
+  for (int c = 0; c < len; c += S) {
+    commit(crow);
     __syncthreads();
     cslot += S;
     if (cslot >= capacity) cslot -= capacity;
-    if (c + S < T1) prefetch(c + S, cslot);
+    if (c + S < len) prefetch(c + S, cslot);
 
     const int rb = crow + g * RPT;  // < H + S: reads stay inside the mirror
+    const int ub = c + g * RPT;     // window offset of this lane's first target
     float2 cur[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) cur[i] = hist[(rb + i) * K + m];
-    const bool full = c + S <= T1;
+
+    auto load_old = [&](float2 (&o)[RPT], int ts) {
+      int r = rb - ts;
+      if (r < 0) r += H;
+      const float2* src = hist + r * K + m;
 #pragma unroll
-    for (int s = 0; s < MAXLW; ++s) {
-      if (s < l_count) {
-        const int ts = tau[s];
-        if (c + S > ts) {  // some target frame of the chunk has a partner
-          int ob = rb - ts;
-          if (ob < 0) ob += H;
-          const float2* old = hist + ob * K + m;
-          if (full && c >= ts) {
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-              const float2 o = old[i * K];
-              const float dx = cur[i].x - o.x, dy = cur[i].y - o.y;
-              ax[s] = fmaf(dx, dx, ax[s]);
-              ay[s] = fmaf(dy, dy, ay[s]);
-            }
+      for (int i = 0; i < RPT; ++i) o[i] = src[i * K];
+    };
+    if (c + S <= len && c >= first_max) {
+      // Every target of the chunk has a partner for every lag of the wave:
+      // unmasked sums, the older rows of lag s+1 read while lag s is summed.
+      float2 o0[RPT], o1[RPT];
+      load_old(o0, tau[0]);
+      dev::static_for<MAXLW>([&](auto SS) {
+        constexpr int s = decltype(SS)::value;
+        if (s < l_count) {
+          if constexpr ((s & 1) == 0) {
+            if (s + 1 < l_count) load_old(o1, tau[s + 1 < MAXLW ? s + 1 : s]);
+            accumulate(cur, o0, s);
           } else {
-            const int64_t tb = c + g * RPT;
+            if (s + 1 < l_count) load_old(o0, tau[s + 1 < MAXLW ? s + 1 : s]);
+            accumulate(cur, o1, s);
+          }
+        }
+      });
+    } else {
+      // Early chunks (some targets precede their partner) and the window's
+      // last, partial chunk.
+#pragma unroll
+      for (int s = 0; s < MAXLW; ++s) {
+        if (s < l_count && c + S > first[s]) {
+          float2 o[RPT];
+          load_old(o, tau[s]);
+          if (c >= first[s] && c + S <= len) {
+            accumulate(cur, o, s);
+          } else {
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-              const int64_t t = tb + i;
-              if (t - ts >= 0 && t < T1) {
-                const float2 o = old[i * K];
-                const float dx = cur[i].x - o.x, dy = cur[i].y - o.y;
+              const int u = ub + i;
+              if (u >= first[s] && u < len) {
+                const float dx = cur[i].x - o[i].x, dy = cur[i].y - o[i].y;
                 ax[s] = fmaf(dx, dx, ax[s]);
                 ay[s] = fmaf(dy, dy, ay[s]);
               }
