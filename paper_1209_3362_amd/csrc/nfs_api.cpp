@@ -34,6 +34,11 @@ struct nfs_plan_s {
   void* ref = nullptr;          // reference frame: first frame of the sequence
   float2* refspec = nullptr;    // its transform on the stored modes
   float2* fscale = nullptr;     // per-frame scales of the current batch
+  int32_t* seg_bin = nullptr;   // binning segments (see nfs::Layout)
+  int32_t* seg_row0 = nullptr;
+  int32_t* bin_seg0 = nullptr;
+  double* part = nullptr;       // per-segment partial sums [segments][lags]
+  long long* part_cnt = nullptr;
   float2* tw = nullptr;
   int32_t* width = nullptr;
   int32_t* offset = nullptr;
@@ -72,8 +77,8 @@ nfs_status flush_pairs(nfs_plan_s* h) {
   for (const nfs::LagGroup& g : L.groups) {
     hipError_t e = nfs::launch_pairs(h->ring, L.modes, L.mode_stride, L.capacity, h->t_done,
                                      h->t_pushed, h->lags + g.first, g.count, g.max_lag,
-                                     h->acc + int64_t(g.first) * L.mode_stride, g.modes, g.hist,
-                                     g.waves, g.per_wave, g.lds, h->stream);
+                                     h->acc + g.first, L.n_lags, g.modes, g.hist, g.waves,
+                                     g.per_wave, g.lds, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "pair kernel launch");
   }
   h->t_done = h->t_pushed;
@@ -153,6 +158,12 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->ref = h->ws + L.off_ref;
   h->refspec = reinterpret_cast<float2*>(h->ws + L.off_refspec);
   h->fscale = reinterpret_cast<float2*>(h->ws + L.off_fscale);
+  const size_t nseg = L.seg_bin.size();
+  h->seg_bin = reinterpret_cast<int32_t*>(h->ws + L.off_segs);
+  h->seg_row0 = h->seg_bin + nseg;
+  h->bin_seg0 = h->seg_row0 + nseg;
+  h->part = reinterpret_cast<double*>(h->ws + L.off_part);
+  h->part_cnt = reinterpret_cast<long long*>(h->ws + L.off_part_cnt);
 
   const std::vector<float> tw = nfs::twiddle_table(L.n);
   hipError_t e = hipMemcpyAsync(h->tw, tw.data(), tw.size() * sizeof(float),
@@ -166,6 +177,15 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->lags, L.lags.data(), L.lags.size() * 4, hipMemcpyHostToDevice,
                        h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->seg_bin, L.seg_bin.data(), nseg * 4, hipMemcpyHostToDevice,
+                       h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->seg_row0, L.seg_row0.data(), nseg * 4, hipMemcpyHostToDevice,
+                       h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h->bin_seg0, L.bin_seg0.data(), L.bin_seg0.size() * 4,
+                       hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     delete h;
@@ -248,9 +268,10 @@ nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
   nfs_status st = flush_pairs(h);
   if (st != NFS_OK) return st;
   const nfs::Layout& L = h->L;
-  hipError_t e = nfs::launch_bins(L.n, L.n_bins, h->acc, L.mode_stride, h->offset, h->lags,
-                                  L.n_lags, h->t_pushed, h->status, D, bin_counts, lag_pairs,
-                                  status, h->stream);
+  hipError_t e = nfs::launch_bins(L.n, L.n_bins, h->acc, L.n_lags, h->offset, h->seg_bin,
+                                  h->seg_row0, int(L.seg_bin.size()), h->bin_seg0, h->part,
+                                  h->part_cnt, h->lags, h->t_pushed, h->status, D, bin_counts,
+                                  lag_pairs, status, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "bin kernel launch");
   return NFS_OK;
 }

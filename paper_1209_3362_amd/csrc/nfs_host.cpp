@@ -128,6 +128,19 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.modes = acc;
   o.mode_stride = int64_t(align_up(size_t(acc), 64));
 
+  // Binning segments, rings in order, kSegRows ring rows each.
+  o.bin_seg0.push_back(0);
+  for (int b = 0; b < o.n_bins; ++b) {
+    int64_t lo, hi;
+    ring_bounds(o.n, o.n_bins, b, &lo, &hi);
+    const int R = int(isqrt_u64(uint64_t(hi - 1)));
+    for (int ky = -R; ky <= R; ky += kSegRows) {
+      o.seg_bin.push_back(b);
+      o.seg_row0.push_back(ky);
+    }
+    o.bin_seg0.push_back(int32_t(o.seg_bin.size()));
+  }
+
   const int max_group = kMaxLagsPerWave * kMaxPairWaves;
   for (int first = 0; first < o.n_lags; first += max_group) {
     LagGroup g;
@@ -154,6 +167,10 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_inter = take(size_t(o.batch) * inter_frame);
   o.off_rowsum = take(size_t(o.batch) * o.n * 8);
   o.off_acc = take(size_t(o.n_lags) * o.mode_stride * 4);
+  const size_t nseg = o.seg_bin.size();
+  o.off_segs = take((2 * nseg + o.bin_seg0.size()) * 4);
+  o.off_part = take(nseg * o.n_lags * 8);
+  o.off_part_cnt = take(nseg * 8);
   o.off_status = take(kAlign);
   o.off_tw = take(size_t(o.n) * 8);
   o.off_width = take(size_t(o.n) * 4);

@@ -26,6 +26,8 @@ constexpr int kMaxPairWaves = 8;
 constexpr int kLdsBytes = 160 * 1024;
 // Largest delay the pair kernel's on-chip history supports (K = 8 modes).
 constexpr int kMaxLag = 2400;
+// Ring rows summed by one workgroup of the binning pass.
+constexpr int kSegRows = 64;
 // Target size of the row-transform intermediate of one batch of frames.
 constexpr size_t kBatchBytes = size_t(128) << 20;
 constexpr int kMaxBatch = 1024;
@@ -67,11 +69,16 @@ struct Layout {
   std::vector<int32_t> row_width;   // [n] stored modes of transform-order row r
   std::vector<int32_t> row_offset;  // [n] first stored index of row r
   std::vector<LagGroup> groups;
+  // Binning segments: segment s covers rows k_y in [seg_row0[s],
+  // seg_row0[s] + kSegRows) of ring seg_bin[s]; ring b owns segments
+  // [bin_seg0[b], bin_seg0[b + 1]).
+  std::vector<int32_t> seg_bin, seg_row0, bin_seg0;
   // Byte offsets into the workspace.
   size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_acc = 0;
   size_t off_status = 0, off_tw = 0, off_width = 0, off_offset = 0;
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
   size_t off_fscale = 0;                // per-frame {sigma, sigma - sigma_ref}
+  size_t off_segs = 0, off_part = 0, off_part_cnt = 0;
   size_t off_lags = 0, total = 0;
 };
 

@@ -34,24 +34,27 @@ hipError_t launch_col_pass(int n, bool reference, const float2* inter, const dou
                            float2* fscale, int32_t* status, hipStream_t s);
 
 // Lag-pair accumulation for target frames [T0, T1) and the lags
-// lags[0..n_lags): acc[l][m] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2 over
-// t in [T0, T1) with t - lag >= 0. Frames [max(0, T0 - max lag), T1) must
-// be in the ring. `modes` per workgroup (64, 32, 16 or 8), `hist` LDS rows,
-// `waves` per workgroup with `per_wave` lags each.
+// lags[0..n_lags): acc[m * acc_pitch + l] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2
+// over t in [T0, T1) with t - lag >= 0 (acc is mode-major). Frames
+// [max(0, T0 - max lag), T1) must be in the ring. `modes` per workgroup
+// (64, 32, 16 or 8), `hist` LDS rows, `waves` per workgroup with
+// `per_wave` lags each.
 hipError_t launch_pairs(const float2* ring, int64_t n_modes, int64_t mode_stride,
-                        int64_t capacity, int64_t T0, int64_t T1,
-                        const int32_t* lags, int n_lags, int max_lag, float* acc,
-                        int modes, int hist, int waves, int per_wave, size_t lds,
-                        hipStream_t s);
+                        int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
+                        int n_lags, int max_lag, float* acc, int acc_pitch, int modes, int hist,
+                        int waves, int per_wave, size_t lds, hipStream_t s);
 
-// Azimuthal binning: D[l][b] = sum_{k in ring b} w(k) acc[l][k] /
-// (C_b * pairs_l) in double, counts[b] = C_b, pairs[l] = max(0, N - lag_l),
-// status_out[0] = *status. pairs_l == 0 gives NaN.
-hipError_t launch_bins(int n, int n_bins, const float* acc, int64_t mode_stride,
-                       const int32_t* row_offset, const int32_t* lags, int n_lags,
-                       int64_t n_frames, const int32_t* status, double* D,
-                       int64_t* counts, int64_t* pairs, int32_t* status_out,
-                       hipStream_t s);
+// Azimuthal binning from the mode-major sums acc [modes][n_lags]: segment
+// partials (segments seg_bin / seg_row0 of kSegRows ring rows), then per
+// ring D[l][b] = sum_{k in ring b} w(k) acc[k][l] / (C_b * pairs_l) in
+// double, counts[b] = C_b, pairs[l] = max(0, N - lag_l), status_out[0]
+// from *status. pairs_l == 0 gives NaN.
+hipError_t launch_bins(int n, int n_bins, const float* acc, int n_lags,
+                       const int32_t* row_offset, const int32_t* seg_bin,
+                       const int32_t* seg_row0, int n_segs, const int32_t* bin_seg0,
+                       double* part, long long* part_cnt, const int32_t* lags,
+                       int64_t n_frames, const int32_t* status, double* D, int64_t* counts,
+                       int64_t* pairs, int32_t* status_out, hipStream_t s);
 
 // Fills `words` 32-bit words at dst with `value`.
 hipError_t launch_fill_u32(void* dst, size_t words, uint32_t value, hipStream_t s);

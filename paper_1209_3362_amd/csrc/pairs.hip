@@ -25,7 +25,7 @@ template <int K>
 __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
     const float2* __restrict__ ring, int64_t n_modes, int64_t mode_stride, int64_t capacity,
     int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags, int max_lag,
-    float* __restrict__ acc, int H, int per_wave) {
+    float* __restrict__ acc, int acc_pitch, int H, int per_wave) {
   constexpr int S = pair_chunk(K); // frames per chunk
   constexpr int G = 64 / K;         // lanes sharing one mode inside a wave
   constexpr int RPT = S / G;        // target rows per lane per chunk
@@ -188,26 +188,33 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
     if (crow >= H) crow -= H;
   }
 
-  // Lanes g = 0..G-1 of one mode hold partial sums over disjoint frames.
-  const bool mode_ok = m0 + m < n_modes;
+  // Lanes g = 0..G-1 of one mode hold partial sums over disjoint frames;
+  // their total goes through LDS so the workgroup adds its K x n_lags block
+  // to the mode-major sums acc[mode][lag] with contiguous accesses.
+  __syncthreads();  // every wave is done with the history
+  float* blk = reinterpret_cast<float*>(hist4);  // [K][n_lags]
 #pragma unroll
   for (int s = 0; s < MAXLW; ++s) {
     if (s < l_count) {
       float v = ax[s] + ay[s];
 #pragma unroll
       for (int o = K; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-      if (g == 0 && mode_ok) {
-        float* p = acc + int64_t(l_begin + s) * mode_stride + m0 + m;
-        *p += v;
-      }
+      if (g == 0) blk[m * n_lags + l_begin + s] = v;
     }
+  }
+  __syncthreads();
+  const int64_t kmax = n_modes - m0 < K ? n_modes - m0 : K;
+  const int nel = int(kmax) * n_lags;
+  for (int e = threadIdx.x; e < nel; e += nthreads) {
+    const int mm = e / n_lags, l = e - mm * n_lags;
+    acc[(m0 + mm) * acc_pitch + l] += blk[e];
   }
 }
 
 template <int K>
 hipError_t pair_launch(const float2* ring, int64_t n_modes, int64_t mode_stride,
                        int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
-                       int n_lags, int max_lag, float* acc, int hist, int waves,
+                       int n_lags, int max_lag, float* acc, int acc_pitch, int hist, int waves,
                        int per_wave, size_t lds, hipStream_t s) {
   // Allow the LDS history beyond the default dynamic limit; a failure here
   // shows up as a launch error below.
@@ -217,7 +224,7 @@ hipError_t pair_launch(const float2* ring, int64_t n_modes, int64_t mode_stride,
   const int launched = waves < 4 ? 4 : waves;  // extra waves only help load
   hipLaunchKernelGGL(pair_kernel<K>, dim3(unsigned(blocks)), dim3(64 * launched), lds, s, ring,
                      n_modes, mode_stride, capacity, T0, T1, lags, n_lags, max_lag, acc,
-                     hist, per_wave);
+                     acc_pitch, hist, per_wave);
   return hipGetLastError();
 }
 
@@ -225,19 +232,20 @@ hipError_t pair_launch(const float2* ring, int64_t n_modes, int64_t mode_stride,
 
 hipError_t launch_pairs(const float2* ring, int64_t n_modes, int64_t mode_stride,
                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
-                        int n_lags, int max_lag, float* acc, int modes, int hist, int waves,
-                        int per_wave, size_t lds, hipStream_t s) {
+                        int n_lags, int max_lag, float* acc, int acc_pitch, int modes, int hist,
+                        int waves, int per_wave, size_t lds, hipStream_t s) {
+#define NFS_PAIR_CASE(KK)                                                                  \
+  case KK:                                                                                 \
+    return pair_launch<KK>(ring, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,     \
+                           max_lag, acc, acc_pitch, hist, waves, per_wave, lds, s);
   switch (modes) {
-    case 64: return pair_launch<64>(ring, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,
-                                    max_lag, acc, hist, waves, per_wave, lds, s);
-    case 32: return pair_launch<32>(ring, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,
-                                    max_lag, acc, hist, waves, per_wave, lds, s);
-    case 16: return pair_launch<16>(ring, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,
-                                    max_lag, acc, hist, waves, per_wave, lds, s);
-    case 8: return pair_launch<8>(ring, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,
-                                  max_lag, acc, hist, waves, per_wave, lds, s);
+    NFS_PAIR_CASE(64)
+    NFS_PAIR_CASE(32)
+    NFS_PAIR_CASE(16)
+    NFS_PAIR_CASE(8)
     default: return hipErrorInvalidValue;
   }
+#undef NFS_PAIR_CASE
 }
 
 }  // namespace nfs
