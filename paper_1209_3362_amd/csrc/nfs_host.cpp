@@ -73,7 +73,7 @@ static bool plan_group(const std::vector<int32_t>& lags, int first, int count,
   for (int K : {64, 32, 16, 8}) {
     const int S = pair_chunk(K);
     const int H = int(align_up(size_t(g->max_lag + 2 * S), S));
-    const size_t lds = size_t(H + S) * K * 8;
+    const size_t lds = size_t(H + pair_mirror(K)) * K * 8;
     if (lds <= size_t(kLdsBytes)) {
       g->modes = K;
       g->hist = H;
@@ -82,18 +82,20 @@ static bool plan_group(const std::vector<int32_t>& lags, int first, int count,
     }
   }
   if (!g->modes) return false;
+  // Wave w takes lags [w * per_wave, (w + 1) * per_wave): pick the wave
+  // count with the fewest unused slots, ties to more waves.
   int best_w = 0, best_waste = std::numeric_limits<int>::max();
   for (int W = 1; W <= kMaxPairWaves; ++W) {
     const int per = (count + W - 1) / W;
-    if (per > kMaxLagsPerWave) continue;
+    if (per > kMaxLagsPerWave || (W - 1) * per >= count) continue;
     const int waste = per * W - count;
-    if (waste <= best_waste) {  // ties go to more waves
+    if (waste <= best_waste) {
       best_waste = waste;
       best_w = W;
     }
   }
   g->waves = best_w;
-  g->per_wave = (count + best_w - 1) / best_w;
+  g->per_wave = best_w ? (count + best_w - 1) / best_w : 0;
   return best_w > 0;
 }
 

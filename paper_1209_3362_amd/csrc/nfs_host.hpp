@@ -21,7 +21,10 @@ constexpr int pair_chunk(int K) { return K == 64 ? 16 : 32; }
 // Most lags one wave of the pair kernel accumulates at once, and most waves
 // per workgroup; a launch handles at most their product.
 constexpr int kMaxLagsPerWave = 8;
-constexpr int kMaxPairWaves = 8;
+constexpr int kMaxPairWaves = 12;
+// LDS rows mirrored after the pair kernel's history ring: a lane reads at
+// most max(S, S*K/64 + kMaxLagsPerWave - 1) consecutive rows.
+constexpr int pair_mirror(int K) { return pair_chunk(K) + kMaxLagsPerWave; }
 // LDS a workgroup may allocate on gfx950.
 constexpr int kLdsBytes = 160 * 1024;
 // Largest delay the pair kernel's on-chip history supports (K = 8 modes).

@@ -37,8 +37,8 @@ hipError_t launch_col_pass(int n, bool reference, const float2* inter, const dou
 // lags[0..n_lags): acc[m * acc_pitch + l] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2
 // over t in [T0, T1) with t - lag >= 0 (acc is mode-major). Frames
 // [max(0, T0 - max lag), T1) must be in the ring. `modes` per workgroup
-// (64, 32, 16 or 8), `hist` LDS rows, `waves` per workgroup with
-// `per_wave` lags each.
+// (64, 32, 16 or 8), `hist` LDS rows; wave w sums lags
+// [w * per_wave, (w + 1) * per_wave) (per_wave <= kMaxLagsPerWave).
 hipError_t launch_pairs(const float2* ring, int64_t n_modes, int64_t mode_stride,
                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                         int n_lags, int max_lag, float* acc, int acc_pitch, int modes, int hist,

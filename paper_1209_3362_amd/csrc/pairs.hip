@@ -5,13 +5,14 @@
 // "differences area" of Fig. 2); the average itself is taken when binning.
 //
 // One workgroup owns K consecutive modes and walks the time axis in chunks
-// of S = 32 frames. The last H frames of its modes live in an LDS ring, so
-// every spectrum value is read from HBM exactly once per launch, however
-// many lags use it; waves split the lag list, and within a wave each lane
-// owns one mode and S*K/64 consecutive target frames. Per pair and mode the
-// inner loop is one LDS read (the older frame), two subtractions and two
-// FMAs. The first S rows of the LDS ring are mirrored after its end so a
-// lane's run of older rows never wraps.
+// of S frames. The last H frames of its modes live in an LDS ring, so every
+// spectrum value is read from HBM exactly once per launch, however many lags
+// use it; waves split the lag list, and within a wave each lane owns one
+// mode and S*K/64 consecutive target frames. Per pair and mode the inner
+// loop is one LDS read (the older frame), two subtractions and two FMAs; a
+// wave whose lags are consecutive integers reads one register window of
+// older frames shared by all its lags instead. The first rows of the LDS
+// ring are mirrored after its end so a lane's run of rows never wraps.
 #include "nfs_device.hpp"
 #include "nfs_host.hpp"
 #include "nfs_kernels.hpp"
@@ -19,17 +20,21 @@
 namespace nfs {
 namespace {
 
-constexpr int MAXLW = kMaxLagsPerWave;
-
-template <int K>
+// K modes per workgroup, MAXLW lag slots per wave (the wave's lags are the
+// contiguous slice [wave * MAXLW, wave * MAXLW + MAXLW) of the list; slots
+// past its end read harmless rows and are not summed).
+template <int K, int MAXLW>
 __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
     const float2* __restrict__ ring, int64_t n_modes, int64_t mode_stride, int64_t capacity,
     int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags, int max_lag,
-    float* __restrict__ acc, int acc_pitch, int H, int per_wave) {
-  constexpr int S = pair_chunk(K); // frames per chunk
+    float* __restrict__ acc, int acc_pitch, int H) {
+  constexpr int S = pair_chunk(K);  // frames per chunk
   constexpr int G = 64 / K;         // lanes sharing one mode inside a wave
   constexpr int RPT = S / G;        // target rows per lane per chunk
-  constexpr int V4 = K / 2;       // float4 (two modes) per ring row of the tile
+  constexpr int V4 = K / 2;         // float4 (two modes) per ring row of the tile
+  constexpr int WIN = RPT + MAXLW - 1;  // register window of a run of consecutive lags
+  constexpr int MR = pair_mirror(K);    // rows mirrored past the end of the LDS ring
+  static_assert(MR >= S && MR >= WIN - 1, "mirror too short for a lane's row run");
   // float4 per thread per chunk; launches have at least 4 waves.
   constexpr int MAXPF = (S * V4 / 256) > 0 ? (S * V4 / 256) : 1;
   extern __shared__ float4 hist4[];
@@ -42,20 +47,23 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
   const int64_t m0 = int64_t(blockIdx.x) * K;
   const int len = int(T1 - T0);  // frames in this window (< capacity)
 
-  // This wave's lags, wave-uniform (scalar registers). A target frame at
-  // window offset u has a partner for lag tau iff u >= first[s].
-  const int l_begin = wave * per_wave;
-  const int l_count = max(0, min(per_wave, n_lags - l_begin));
+  // This wave's lags, in scalar registers. A target frame at window offset
+  // u has a partner for lag tau[s] iff u >= first[s].
+  const int l_begin = wave * MAXLW;
+  const int l_count = max(0, min(MAXLW, n_lags - l_begin));
   int tau[MAXLW], first[MAXLW];
-  int first_max = 0;
 #pragma unroll
   for (int s = 0; s < MAXLW; ++s) {
     const int ts = s < l_count ? lags[l_begin + s] : 0;
     tau[s] = __builtin_amdgcn_readfirstlane(ts);
     const int64_t f = int64_t(ts) - T0;
     first[s] = __builtin_amdgcn_readfirstlane(int(f > 0 ? f : 0));
-    first_max = max(first_max, first[s]);
   }
+  // Consecutive lags tau[0], tau[0]+1, ... share one register window.
+  bool consecutive = MAXLW > 1 && l_count > 1;
+#pragma unroll
+  for (int s = 1; s < MAXLW; ++s)
+    if (s < l_count && tau[s] != tau[0] + s) consecutive = false;
 
   // Window offset u lives in LDS row (u + max_lag) mod H.
   auto slot_row = [&](int64_t slot) -> const float4* {
@@ -63,7 +71,7 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
   };
   auto put_row = [&](int row, int col2, float4 val) {
     hist4[(row * K) / 2 + col2] = val;
-    if (row < S) hist4[((row + H) * K) / 2 + col2] = val;
+    if (row < MR) hist4[((row + H) * K) / 2 + col2] = val;
   };
 
   // History from earlier windows: frames [max(0, T0 - max_lag), T0).
@@ -111,7 +119,8 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
 #pragma unroll
   for (int s = 0; s < MAXLW; ++s) ax[s] = ay[s] = 0.f;
 
-  auto accumulate = [&](const float2 (&cur)[RPT], const float2 (&old)[RPT], int s) {
+  // |cur[i] - old[i]|^2 into lag slot s.
+  auto acc_plain = [&](const float2* cur, const float2* old, int s) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const float dx = cur[i].x - old[i].x, dy = cur[i].y - old[i].y;
@@ -119,6 +128,23 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
       ay[s] = fmaf(dy, dy, ay[s]);
     }
   };
+  // The same with targets that have no partner yet (u < first) or lie past
+  // the window end zeroed by selects, not branches.
+  auto acc_masked = [&](const float2* cur, const float2* old, int s, int ub) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int u = ub + i;
+      const bool ok = (u >= first[s]) & (u < len);
+      const float dx = ok ? cur[i].x - old[i].x : 0.f;
+      const float dy = ok ? cur[i].y - old[i].y : 0.f;
+      ax[s] = fmaf(dx, dx, ax[s]);
+      ay[s] = fmaf(dy, dy, ay[s]);
+    }
+  };
+  int first_max = 0;
+#pragma unroll
+  for (int s = 0; s < MAXLW; ++s)
+    if (s < l_count) first_max = max(first_max, first[s]);
 
   int crow = max_lag % H;         // LDS row of the chunk's first frame
   int64_t cslot = T0 % capacity;  // ring slot of the chunk's first frame
@@ -130,59 +156,71 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
     if (cslot >= capacity) cslot -= capacity;
     if (c + S < len) prefetch(c + S, cslot);
 
-    const int rb = crow + g * RPT;  // < H + S: reads stay inside the mirror
+    const int rb = crow + g * RPT;  // reads stay inside the ring and its mirror
     const int ub = c + g * RPT;     // window offset of this lane's first target
+    const bool full = c + S <= len;
     float2 cur[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) cur[i] = hist[(rb + i) * K + m];
-
-    auto load_old = [&](float2 (&o)[RPT], int ts) {
+    auto older = [&](int ts) {
       int r = rb - ts;
       if (r < 0) r += H;
-      const float2* src = hist + r * K + m;
+      return hist + r * K + m;
+    };
+
+    // Older rows of a lag slot; slots past l_count have tau = 0 and read the
+    // current rows, so every read is in bounds and unconditional.
+    auto load_old = [&](float2 (&o)[RPT], int ts) {
+      const float2* src = older(ts);
 #pragma unroll
       for (int i = 0; i < RPT; ++i) o[i] = src[i * K];
     };
-    if (c + S <= len && c >= first_max) {
-      // Every target of the chunk has a partner for every lag of the wave:
-      // unmasked sums, the older rows of lag s+1 read while lag s is summed.
+    if (full && c >= first_max) {
+      // Every target of the chunk has a partner for every lag of the wave.
+      if (consecutive) {
+        // Rows rb - tau[0] - (MAXLW-1) .. rb - tau[0] + RPT - 1 serve every
+        // lag of the run: lag tau[0] + s reads win[MAXLW - 1 - s + i].
+        float2 win[WIN];
+        const float2* src = older(tau[0] + MAXLW - 1);
+#pragma unroll
+        for (int i = 0; i < WIN; ++i) win[i] = src[i * K];
+        dev::static_for<MAXLW>([&](auto SS) {
+          constexpr int s = decltype(SS)::value;
+          if (s < l_count) acc_plain(cur, win + (MAXLW - 1 - s), s);
+        });
+      } else {
+        // The older rows of slot s+1 are read while slot s is summed.
+        float2 o0[RPT], o1[RPT];
+        load_old(o0, tau[0]);
+        dev::static_for<MAXLW>([&](auto SS) {
+          constexpr int s = decltype(SS)::value;
+          constexpr int nx = s + 1 < MAXLW ? s + 1 : s;
+          if constexpr ((s & 1) == 0) {
+            if constexpr (s + 1 < MAXLW) load_old(o1, tau[nx]);
+            if (s < l_count) acc_plain(cur, o0, s);
+          } else {
+            if constexpr (s + 1 < MAXLW) load_old(o0, tau[nx]);
+            if (s < l_count) acc_plain(cur, o1, s);
+          }
+        });
+      }
+    } else {
+      // Early chunks (some targets precede their partner) and the window's
+      // last, partial chunk.
       float2 o0[RPT], o1[RPT];
       load_old(o0, tau[0]);
       dev::static_for<MAXLW>([&](auto SS) {
         constexpr int s = decltype(SS)::value;
-        if (s < l_count) {
-          if constexpr ((s & 1) == 0) {
-            if (s + 1 < l_count) load_old(o1, tau[s + 1 < MAXLW ? s + 1 : s]);
-            accumulate(cur, o0, s);
-          } else {
-            if (s + 1 < l_count) load_old(o0, tau[s + 1 < MAXLW ? s + 1 : s]);
-            accumulate(cur, o1, s);
-          }
+        constexpr int nx = s + 1 < MAXLW ? s + 1 : s;
+        const bool act = s < l_count && c + S > first[s];
+        if constexpr ((s & 1) == 0) {
+          if constexpr (s + 1 < MAXLW) load_old(o1, tau[nx]);
+          if (act) acc_masked(cur, o0, s, ub);
+        } else {
+          if constexpr (s + 1 < MAXLW) load_old(o0, tau[nx]);
+          if (act) acc_masked(cur, o1, s, ub);
         }
       });
-    } else {
-      // Early chunks (some targets precede their partner) and the window's
-      // last, partial chunk.
-#pragma unroll
-      for (int s = 0; s < MAXLW; ++s) {
-        if (s < l_count && c + S > first[s]) {
-          float2 o[RPT];
-          load_old(o, tau[s]);
-          if (c >= first[s] && c + S <= len) {
-            accumulate(cur, o, s);
-          } else {
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-              const int u = ub + i;
-              if (u >= first[s] && u < len) {
-                const float dx = cur[i].x - o[i].x, dy = cur[i].y - o[i].y;
-                ax[s] = fmaf(dx, dx, ax[s]);
-                ay[s] = fmaf(dy, dy, ay[s]);
-              }
-            }
-          }
-        }
-      }
     }
     crow += S;
     if (crow >= H) crow -= H;
@@ -211,21 +249,44 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
   }
 }
 
-template <int K>
+template <int K, int P>
 hipError_t pair_launch(const float2* ring, int64_t n_modes, int64_t mode_stride,
                        int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                        int n_lags, int max_lag, float* acc, int acc_pitch, int hist, int waves,
-                       int per_wave, size_t lds, hipStream_t s) {
+                       size_t lds, hipStream_t s) {
   // Allow the LDS history beyond the default dynamic limit; a failure here
   // shows up as a launch error below.
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_kernel<K>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_kernel<K, P>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
   const int64_t blocks = (n_modes + K - 1) / K;
   const int launched = waves < 4 ? 4 : waves;  // extra waves only help load
-  hipLaunchKernelGGL(pair_kernel<K>, dim3(unsigned(blocks)), dim3(64 * launched), lds, s, ring,
-                     n_modes, mode_stride, capacity, T0, T1, lags, n_lags, max_lag, acc,
-                     acc_pitch, hist, per_wave);
+  hipLaunchKernelGGL((pair_kernel<K, P>), dim3(unsigned(blocks)), dim3(64 * launched), lds, s,
+                     ring, n_modes, mode_stride, capacity, T0, T1, lags, n_lags, max_lag, acc,
+                     acc_pitch, hist);
   return hipGetLastError();
+}
+
+template <int K>
+hipError_t pair_dispatch(int per_wave, const float2* ring, int64_t n_modes,
+                         int64_t mode_stride, int64_t capacity, int64_t T0, int64_t T1,
+                         const int32_t* lags, int n_lags, int max_lag, float* acc,
+                         int acc_pitch, int hist, int waves, size_t lds, hipStream_t s) {
+#define NFS_PAIR_P(PP)                                                                     \
+  case PP:                                                                                 \
+    return pair_launch<K, PP>(ring, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,  \
+                              max_lag, acc, acc_pitch, hist, waves, lds, s);
+  switch (per_wave) {
+    NFS_PAIR_P(1)
+    NFS_PAIR_P(2)
+    NFS_PAIR_P(3)
+    NFS_PAIR_P(4)
+    NFS_PAIR_P(5)
+    NFS_PAIR_P(6)
+    NFS_PAIR_P(7)
+    NFS_PAIR_P(8)
+    default: return hipErrorInvalidValue;
+  }
+#undef NFS_PAIR_P
 }
 
 }  // namespace
@@ -236,8 +297,8 @@ hipError_t launch_pairs(const float2* ring, int64_t n_modes, int64_t mode_stride
                         int waves, int per_wave, size_t lds, hipStream_t s) {
 #define NFS_PAIR_CASE(KK)                                                                  \
   case KK:                                                                                 \
-    return pair_launch<KK>(ring, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,     \
-                           max_lag, acc, acc_pitch, hist, waves, per_wave, lds, s);
+    return pair_dispatch<KK>(per_wave, ring, n_modes, mode_stride, capacity, T0, T1, lags, \
+                             n_lags, max_lag, acc, acc_pitch, hist, waves, lds, s);
   switch (modes) {
     NFS_PAIR_CASE(64)
     NFS_PAIR_CASE(32)

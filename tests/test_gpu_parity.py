@@ -109,6 +109,20 @@ def test_ring_wrap_and_push_chunking():
         assert_D_close(D, full[0], rtol=1e-6)
 
 
+def test_consecutive_lags_across_windows():
+    # Waves whose lags are consecutive integers share a register window of
+    # older frames; check it with ring wrap, chunked pushes and early chunks.
+    cfg = gen.config("c1", n=32, N=150, n_bins=16)
+    lags = list(range(0, 23)) + [30, 31, 32, 33, 47]
+    say("consecutive lags 0..22 + 30..33 + 47, 150 frames 32x32, capacity 60, chunks 9")
+    f = gen.make_stack(cfg, 12)
+    ref = oracle.structure_function(f.numpy(), lags, 16)
+    for cap, chunk in [(150, None), (60, 9), (48, 1)]:
+        D, C, P, st = run_plan(f, lags, 16, "f32", capacity=cap, chunk=chunk)
+        assert np.array_equal(P, ref["pairs"])
+        assert_D_close(D, ref["D"], rtol=1e-4)
+
+
 def test_run_twice_is_bitwise_identical():
     cfg = gen.config("c1")
     say("determinism: c1 twice")
