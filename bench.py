@@ -27,6 +27,37 @@ VALU_LANE_OPS = 256 * 64 * 2.4e9
 FP32_FMA_PEAK_TFLOPS = VALU_LANE_OPS * 2 / 1e12  # 78.6
 
 
+PAIR_COUNTERS = os.path.join(ROOT, "profiles", "pair_kernel_1000x1024_counters.md")
+PAIR_SOURCES = ["paper_1209_3362_amd/csrc/pairs.hip", "paper_1209_3362_amd/csrc/nfs_host.hpp",
+                "paper_1209_3362_amd/csrc/nfs_host.cpp"]
+
+
+def pair_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in PAIR_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def pair_traffic():
+    """HBM bytes per pair-kernel launch from the committed counter summary,
+    or None when it is missing or the kernel's sources changed since."""
+    try:
+        fields = {}
+        with open(PAIR_COUNTERS) as f:
+            for line in f:
+                if ":" in line and line.startswith("- "):
+                    k, v = line[2:].split(":", 1)
+                    fields[k.strip()] = v.strip().strip("`")
+        if fields.get("source_sha256") != pair_source_digest():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -35,6 +66,9 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-frames", type=int, default=80)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB device buffer 5 times (known bytes), to scale "
+                         "memory counters of the same profiler run")
     ap.add_argument("--frames-cache", default=None,
                     help="load the stack from this .npy if it exists, else draw it and "
                          "save it there (lets profiler runs skip the generator)")
@@ -61,8 +95,25 @@ def cpu_baseline(frames_gpu, cfg, n_frames):
                        f"full-plane oracle, {dt:.1f} s on one host thread")}
 
 
+def copy_calibration():
+    """Five device-to-device copies of 1 GiB: 1 GiB read and 1 GiB written each."""
+    import torch
+    n = 1 << 30
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": n, "copy_bytes_written_per_launch": n,
+                      "launches": 5}))
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -170,7 +221,7 @@ def main():
             "peak": FP32_FMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": pair_tflops / FP32_FMA_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": pair_traffic(),
             "valu_issue_frac": 4.0 * pair_k / (ms_pair * 1e-3) / VALU_LANE_OPS,
         },
     }

@@ -10,7 +10,12 @@
 // twiddled and exchanged once through LDS, and a second register DFT
 // finishes the transform. Twiddles of the register DFTs are compile-time
 // constants built in double; the exchange twiddles come from a table built
-// in double on the host and rounded once to float.
+// in double on the host and rounded once to float, kept in LDS with one
+// pad entry per 8 (fewer bank conflicts for strided reads).
+//
+// The intermediate between the passes is [frame][n/4 tiles][n rows][2]:
+// tiles of two columns, so a row pass wave writes 64-byte runs and a column
+// pass wave reads 128-byte runs.
 #include "nfs_device.hpp"
 #include "nfs_kernels.hpp"
 
@@ -21,17 +26,30 @@ namespace {
 
 constexpr int kLdsBudget = 80 * 1024;  // per workgroup, so two fit per CU
 
-constexpr int fit_rows(int r, int pitch) {
-  while (r > 1 && r * pitch * 8 > kLdsBudget) r /= 2;
+// Exchange twiddle table in LDS: entry m at m + m/8.
+__host__ __device__ constexpr int tw_skew(int m) { return m + (m >> 3); }
+constexpr int tw_len(int n) { return n + n / 8; }
+
+constexpr int fit_rows(int r, int pitch, int fixed) {
+  while (r > 1 && r * pitch * 8 + fixed > kLdsBudget) r /= 2;
   return r;
 }
 // LDS column pitch congruent to 2 mod 16 complex values, so 8 columns x 2
 // rows of 8-byte accesses fall in 16 distinct bank pairs.
 constexpr int pad_2mod16(int v) { return v + ((2 - v % 16) + 16) % 16; }
-constexpr int fit_cols(int pitch) {
+constexpr int fit_cols(int pitch, int fixed) {
   int c = 8;
-  while (c > 1 && c * pitch * 8 > kLdsBudget) c /= 2;
+  while (c > 1 && c * pitch * 8 + fixed > kLdsBudget) c /= 2;
   return c;
+}
+
+// Orders a wave's LDS writes before later LDS reads of other lanes of the
+// same wave: the exchanges of the row pass never leave a wave, so no
+// workgroup barrier is needed.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <int N>
@@ -41,11 +59,12 @@ struct RowCfg {
   static constexpr int P2 = H / P1;
   static constexpr int Q = P2 / P1;
   static constexpr int PITCH = P2 * (P1 + 1) + 4;    // LDS complex values per row
-  static constexpr int R0 = fit_rows(256 / P1, PITCH);
+  static constexpr int R0 = fit_rows(256 / P1, PITCH, tw_len(N) * 8);
   static constexpr int R = R0 < N ? R0 : N;          // rows per workgroup
   static constexpr int THREADS = R * P1;
   static constexpr int RB = N / R;                   // row blocks per frame
-  static constexpr int TILES = H / 8;                // 8-column tiles of the intermediate
+  static constexpr int TILES = H / 2;                // 2-column tiles of the intermediate
+  static_assert(64 % P1 == 0, "a row's threads must sit in one wave");
 };
 
 template <int N>
@@ -54,10 +73,10 @@ struct ColCfg {
   static constexpr int P2 = N / P1;
   static constexpr int Q = P2 / P1;
   static constexpr int CP = pad_2mod16(P2 * (P1 + 1));
-  static constexpr int CW = fit_cols(CP);            // columns per workgroup
+  static constexpr int CW = fit_cols(CP, tw_len(N) * 8);  // columns per workgroup
   static constexpr int THREADS = CW * P1;
   static constexpr int GROUPS = (N / 2) / CW;        // column groups per frame
-  static constexpr int TILES = N / 16;
+  static constexpr int TILES = N / 4;
 };
 
 // Frames one workgroup of a pass loops over: enough workgroups to give
@@ -89,9 +108,11 @@ __device__ __forceinline__ typename RawPair<T>::type load_pair(const T* p) {
 // Row pass. Real row u of N pixels (minus the reference row, times the
 // window) -> z[j] = u[2j] + i u[2j+1] (H points), Z = DFT_H(z), then
 // X[k] = (Z[k] + conj Z[H-k])/2 - i W_N^k (Z[k] - conj Z[H-k])/2 for
-// k = 0..H-1 (the real-input split; X[H] is never binned). A workgroup owns
-// R rows and loops over up to `per_group` frames of the batch, loading the
-// next frame's pixels while it transforms the current one.
+// k = 0..H-1 (the real-input split; X[H] is never binned). A row's P1
+// threads sit in one wave and only they touch the row's LDS, so the frame
+// loop has no workgroup barrier. A workgroup owns R rows and loops over up
+// to `per_group` frames of the batch, loading the next frame's pixels while
+// it transforms the current one.
 template <int N, typename T, bool WIN>
 __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
     const T* __restrict__ frames, const T* __restrict__ ref, const float* __restrict__ window,
@@ -103,18 +124,17 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
   constexpr int H = C::H, P1 = C::P1, P2 = C::P2, Q = C::Q, R = C::R, RB = C::RB;
   constexpr int PITCH = C::PITCH, THREADS = C::THREADS, TILES = C::TILES;
   __shared__ float2 lds[R * PITCH];
-  __shared__ float2 twl[N];
+  __shared__ float2 twl[tw_len(N)];
 
   const int tid = threadIdx.x;
   const int rl = tid / P1, j1 = tid % P1;
   const int rblk = blockIdx.x % RB;
   const int f_begin = (blockIdx.x / RB) * per_group;
   const int f_end = min(nframes, f_begin + per_group);
-  const int y0 = rblk * R;
-  const int y = y0 + rl;
+  const int y = rblk * R + rl;
   float2* row_lds = lds + rl * PITCH;
 
-  for (int i = tid; i < N; i += THREADS) twl[i] = tw[i];
+  for (int i = tid; i < N; i += THREADS) twl[tw_skew(i)] = tw[i];
 
   // Up to 32 pixel pairs per thread the reference row stays in registers and
   // the next frame is prefetched; larger rows reload both from cache.
@@ -139,7 +159,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
     for (int j2 = 0; j2 < P2; ++j2) refv[j2] = ref_pair(j2);
     if (f_begin < f_end) load_raw(f_begin);
   }
-  __syncthreads();
+  __syncthreads();  // the twiddle table is shared by all rows
 
   for (int f = f_begin; f < f_end; ++f) {
     float2 v[P2];
@@ -198,10 +218,10 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
     static_for<P2>([&](auto K2) {
       constexpr int k2 = decltype(K2)::value;
       float2 yv = v[bitrev<P2>(k2)];
-      if constexpr (k2 != 0) yv = cmul(yv, twl[(2 * j1 * k2) & (N - 1)]);
+      if constexpr (k2 != 0) yv = cmul(yv, twl[tw_skew((2 * j1 * k2) & (N - 1))]);
       row_lds[k2 * (P1 + 1) + j1] = yv;
     });
-    __syncthreads();
+    wave_lds_sync();
 
     // Second level: for k2 = j1 + q P1, DFT over j1 gives Z[k2 + P2 k1].
     float2 z[Q][P1];
@@ -217,32 +237,27 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
         z[q][k1] = w[bitrev<P1>(k1)];
       });
     });
-    __syncthreads();
+    wave_lds_sync();
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
       for (int k1 = 0; k1 < P1; ++k1) row_lds[(j1 + q * P1) + P2 * k1] = z[q][k1];
-    __syncthreads();
+    wave_lds_sync();
 
-    // Real-input split and store into 8-column tiles: for a tile the rows of
-    // this workgroup are contiguous in the intermediate.
-    float2* dst = inter + (int64_t(f) * TILES * N + y0) * 8;
+    // Real-input split of this thread's outputs k = j1 + P1 i, stored into
+    // 2-column tiles of the intermediate.
+    float2* dst = inter + ((int64_t(f) * TILES + (j1 >> 1)) * N + y) * 2 + (j1 & 1);
 #pragma unroll
     for (int i = 0; i < P2; ++i) {
-      const int idx = tid + i * THREADS;
-      const int c = idx & 7;
-      const int rr = (idx >> 3) & (R - 1);
-      const int tile = idx / (8 * R);
-      const int k = tile * 8 + c;
-      const float2 zk = lds[rr * PITCH + k];
-      const float2 zm = lds[rr * PITCH + ((H - k) & (H - 1))];
+      const int k = j1 + P1 * i;
+      const float2 zk = row_lds[k];
+      const float2 zm = row_lds[(H - k) & (H - 1)];
       const float2 e = make_float2(zk.x + zm.x, zk.y - zm.y);   // Z[k] + conj Z[H-k]
       const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);   // Z[k] - conj Z[H-k]
-      const float2 wd = cmul(d, twl[k]);
-      dst[(int64_t(tile) * N + rr) * 8 + c] =
-          make_float2(0.5f * (e.x + wd.y), 0.5f * (e.y - wd.x));
+      const float2 wd = cmul(d, twl[tw_skew(k)]);
+      dst[int64_t(i) * (P1 / 2) * N * 2] = make_float2(0.5f * (e.x + wd.y), 0.5f * (e.y - wd.x));
     }
-    __syncthreads();  // LDS is rewritten by the next frame
+    wave_lds_sync();  // the row's LDS is rewritten by the next frame
   }
 }
 
@@ -299,18 +314,17 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
   constexpr int P1 = C::P1, P2 = C::P2, Q = C::Q, CP = C::CP, CW = C::CW;
   constexpr int THREADS = C::THREADS, GROUPS = C::GROUPS, TILES = C::TILES;
   __shared__ float2 lds[CW * CP];
-  __shared__ float2 twl[N];
+  __shared__ float2 twl[tw_len(N)];
 
   const int grp = blockIdx.x % GROUPS;
   const int f_begin = (blockIdx.x / GROUPS) * per_group;
   const int f_end = min(nframes, f_begin + per_group);
   const int kx0 = grp * CW;
-  const int tile = kx0 / 8, c0 = kx0 % 8;
   const int tid = threadIdx.x;
   const int c = tid % CW, j1 = tid / CW;
   const int kx = kx0 + c;
 
-  for (int i = tid; i < N; i += THREADS) twl[i] = tw[i];
+  for (int i = tid; i < N; i += THREADS) twl[tw_skew(i)] = tw[i];
 
   // Outputs of this thread: rows r = (j1 + q P1) + P2 k1 of column kx. Up
   // to 32 outputs per thread their store index and reference value stay in
@@ -337,9 +351,9 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
   }
 
   auto load_cols = [&](float2 (&v)[P2], int f) {
-    const float2* src = inter + (int64_t(f) * TILES + tile) * N * 8 + c0 + c;
+    const float2* src = inter + (int64_t(f) * TILES + (kx >> 1)) * N * 2 + (kx & 1);
 #pragma unroll
-    for (int j2 = 0; j2 < P2; ++j2) v[j2] = src[(j1 + P1 * j2) * 8];
+    for (int j2 = 0; j2 < P2; ++j2) v[j2] = src[(j1 + P1 * j2) * 2];
   };
   float2 v[P2];
   if (CACHE && f_begin < f_end) load_cols(v, f_begin);
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
     static_for<P2>([&](auto K2) {
       constexpr int k2 = decltype(K2)::value;
       float2 yv = v[bitrev<P2>(k2)];
-      if constexpr (k2 != 0) yv = cmul(yv, twl[(j1 * k2) & (N - 1)]);
+      if constexpr (k2 != 0) yv = cmul(yv, twl[tw_skew((j1 * k2) & (N - 1))]);
       col_lds[k2 * (P1 + 1) + j1] = yv;
     });
     __syncthreads();

@@ -13,7 +13,7 @@ namespace nfs {
 // transformed. frames: [nframes][n][n] of u16 (in_dtype 0) or f32 (1);
 // ref: [n][n] of the same type subtracted from every frame first, or null;
 // window: [n][n] multiplied in after the subtraction, or null. Writes inter
-// [nframes][n/16][n][8] complex (8-column tiles) and rowsum [nframes][n].
+// [nframes][n/4][n][2] complex (2-column tiles) and rowsum [nframes][n].
 hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* ref,
                            const float* window, int nframes, float2* inter, double* rowsum,
                            const float2* tw, hipStream_t s);
