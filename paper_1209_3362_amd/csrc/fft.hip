@@ -316,8 +316,13 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
   __shared__ float2 lds[CW * CP];
   __shared__ float2 twl[tw_len(N)];
 
-  const int grp = blockIdx.x % GROUPS;
-  const int f_begin = (blockIdx.x / GROUPS) * per_group;
+  // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
+  // neighbouring column groups of a frame (which write the two halves of
+  // the same 128-byte lines of the stored rows) share an XCD and its L2.
+  int bid = blockIdx.x;
+  if (gridDim.x % 8 == 0) bid = (bid % 8) * int(gridDim.x / 8) + bid / 8;
+  const int grp = bid % GROUPS;
+  const int f_begin = (bid / GROUPS) * per_group;
   const int f_end = min(nframes, f_begin + per_group);
   const int kx0 = grp * CW;
   const int tid = threadIdx.x;
