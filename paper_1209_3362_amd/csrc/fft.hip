@@ -77,6 +77,9 @@ struct ColCfg {
   static constexpr int THREADS = CW * P1;
   static constexpr int GROUPS = (N / 2) / CW;        // column groups per frame
   static constexpr int TILES = N / 4;
+  // Two workgroups per CU while the per-thread store offsets fit the
+  // register budget of two waves per SIMD.
+  static constexpr int MINW = Q * P1 <= 32 ? 2 : 1;
 };
 
 // Frames one workgroup of a pass loops over: enough workgroups to give
@@ -86,6 +89,14 @@ inline int frames_per_group(int nframes, int groups_per_frame) {
   if (f < 1) f = 1;
   if (f > 8) f = 8;
   return f;
+}
+
+// Two row-pass workgroups per CU where a thread's state fits the register
+// budget of two waves per SIMD without spilling (integer pixels, no window,
+// up to 1024 pixels per row).
+template <int N, typename T, bool WIN>
+constexpr int row_min_waves() {
+  return N <= 512 || (N == 1024 && std::is_same<T, uint16_t>::value && !WIN) ? 2 : 1;
 }
 
 template <typename T>
@@ -114,7 +125,7 @@ __device__ __forceinline__ typename RawPair<T>::type load_pair(const T* p) {
 // to `per_group` frames of the batch, loading the next frame's pixels while
 // it transforms the current one.
 template <int N, typename T, bool WIN>
-__global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
+__global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN>())) void row_pass_kernel(
     const T* __restrict__ frames, const T* __restrict__ ref, const float* __restrict__ window,
     int nframes, int per_group, float2* __restrict__ inter, double* __restrict__ rowsum,
     const float2* __restrict__ tw) {
@@ -265,13 +276,14 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS) void row_pass_kernel(
 // Frame scales from the row sums, in a fixed order (strided partial sums,
 // butterfly per wave, waves in index order). REF: the rows were the
 // reference image; refscal = {S_ref, n^2/S_ref}. Otherwise the rows were
-// (image - reference): S = S_ref + sum, sigma = n^2/S and
-// fscale[f] = {sigma, sigma - sigma_ref}; a frame whose S is not positive
-// and finite gets sigma = 0 and sets bit 0 of *status.
+// (image - reference) of frame t0 + f: S = S_ref + sum, sigma = n^2/S and
+// fscale[(t0 + f) mod capacity] = {sigma, sigma - sigma_ref}; a frame whose
+// S is not positive and finite gets sigma = 0 and sets bit 0 of *status.
 template <bool REF>
 __global__ __launch_bounds__(256) void frame_scale_kernel(int n, const double* __restrict__ rowsum,
                                                           double* __restrict__ refscal,
                                                           float2* __restrict__ fscale,
+                                                          int64_t t0, int64_t capacity,
                                                           int32_t* __restrict__ status) {
   __shared__ double red[4];
   const int f = blockIdx.x, tid = threadIdx.x;
@@ -290,7 +302,7 @@ __global__ __launch_bounds__(256) void frame_scale_kernel(int n, const double* _
       refscal[0] = total;
       refscal[1] = sigma;
     } else {
-      fscale[f] = make_float2(float(sigma), float(sigma - refscal[1]));
+      fscale[(t0 + f) % capacity] = make_float2(float(sigma), float(sigma - refscal[1]));
       if (bad) atomicOr(status, 1);
     }
   }
@@ -298,16 +310,17 @@ __global__ __launch_bounds__(256) void frame_scale_kernel(int n, const double* _
 
 // ---------------------------------------------------------------------------
 // Column pass over CW columns: DFT_N over the rows of each frame of the
-// group. REF: store the reference transform unscaled in refspec. Otherwise
-// store sigma * X + (sigma - sigma_ref) * refspec (= I_t - sigma_ref *
-// F[reference], fluctuation-sized) with I_t(0) - sigma_ref F[ref](0) := 0,
-// at the stored modes (k_x < row_width[r]) of ring slot (t0 + f) mod
-// capacity. Per-thread store addresses and reference values are loaded
-// once; the next frame's columns are loaded during the second level.
+// group. REF: store the reference transform F[reference] unscaled in
+// refspec. Otherwise store sigma * X (X = F[frame - reference]) into ring
+// slot (t0 + f) mod capacity, sigma from that slot's fscale entry. Both
+// store 0 at k = 0 and only the stored modes (k_x < row_width[r]); the
+// pair kernel adds (sigma - sigma_ref) * refspec when it reads a slot.
+// Per-thread store offsets are computed once; the next frame's columns are
+// loaded during the second level.
 template <int N, bool REF>
-__global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
+__global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_kernel(
     const float2* __restrict__ inter, const float2* __restrict__ fscale, int nframes,
-    int per_group, int64_t t0, int64_t capacity, int64_t mode_stride,
+    int per_group, int64_t t0, int64_t capacity, int64_t mode_stride, int64_t n_modes,
     const int32_t* __restrict__ row_width, const int32_t* __restrict__ row_offset,
     const float2* __restrict__ tw, float2* __restrict__ ring, float2* __restrict__ refspec) {
   using C = ColCfg<N>;
@@ -331,28 +344,24 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
 
   for (int i = tid; i < N; i += THREADS) twl[tw_skew(i)] = tw[i];
 
-  // Outputs of this thread: rows r = (j1 + q P1) + P2 k1 of column kx. Up
-  // to 32 outputs per thread their store index and reference value stay in
-  // registers across frames; more are looked up again per frame.
+  // Outputs of this thread: rows r = (j1 + q P1) + P2 k1 of column kx,
+  // stored at byte offset 8 (row_offset[r] + kx) of the spectrum, or not
+  // at all (kDropOffset) when kx >= row_width[r]. Up to 32 outputs per
+  // thread the offsets stay in registers across frames; more are looked up
+  // again per frame.
   constexpr bool CACHE = Q * P1 <= 32;
   constexpr int QC = CACHE ? Q : 1, PC = CACHE ? P1 : 1;
-  auto store_index = [&](int q, int k1) {
+  auto store_offset = [&](int q, int k1) -> uint32_t {
     const int r = (j1 + q * P1) + P2 * k1;
-    return kx < row_width[r] ? row_offset[r] + kx : -1;
+    const int w = row_width[r], o = row_offset[r];  // both loads unconditional
+    return kx < w ? uint32_t(o + kx) * 8u : kDropOffset;
   };
-  int at[QC][PC];
-  float2 rv[QC][PC];
+  uint32_t at[QC][PC];
   if constexpr (CACHE) {
 #pragma unroll
     for (int q = 0; q < Q; ++q)
 #pragma unroll
-      for (int k1 = 0; k1 < P1; ++k1) {
-        at[q][k1] = store_index(q, k1);
-        rv[q][k1] = make_float2(0.f, 0.f);
-        if constexpr (!REF) {
-          if (at[q][k1] >= 0) rv[q][k1] = refspec[at[q][k1]];
-        }
-      }
+      for (int k1 = 0; k1 < P1; ++k1) at[q][k1] = store_offset(q, k1);
   }
 
   auto load_cols = [&](float2 (&v)[P2], int f) {
@@ -363,6 +372,8 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
   float2 v[P2];
   if (CACHE && f_begin < f_end) load_cols(v, f_begin);
   float2* col_lds = lds + c * CP;
+  int64_t slot = (t0 + f_begin) % capacity;
+  const uint32_t spec_bytes = uint32_t(n_modes) * 8u;
   __syncthreads();
 
   for (int f = f_begin; f < f_end; ++f) {
@@ -379,13 +390,9 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
       if (f + 1 < f_end) load_cols(v, f + 1);
     }
 
-    float scale = 1.f, dscale = 0.f;
-    if constexpr (!REF) {
-      const float2 sc = fscale[f];
-      scale = sc.x;
-      dscale = sc.y;
-    }
-    float2* dst = REF ? refspec : ring + ((t0 + f) % capacity) * mode_stride;
+    float scale = 1.f;
+    if constexpr (!REF) scale = fscale[slot].x;
+    const BufferRsrc dst = make_buffer(REF ? refspec : ring + slot * mode_stride, spec_bytes);
     static_for<Q>([&](auto QQ) {
       constexpr int q = decltype(QQ)::value;
       const int k2 = j1 + q * P1;
@@ -395,21 +402,21 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void col_pass_kernel(
       dft<P1>(w);
       static_for<P1>([&](auto K1) {
         constexpr int k1 = decltype(K1)::value;
-        int a;
-        if constexpr (CACHE) a = at[q][k1]; else a = store_index(q, k1);
-        if (a >= 0) {
-          float2 X = w[bitrev<P1>(k1)];
-          if constexpr (!REF) {
-            float2 Rv;
-            if constexpr (CACHE) Rv = rv[q][k1]; else Rv = refspec[a];
-            X.x = fmaf(dscale, Rv.x, scale * X.x);
-            X.y = fmaf(dscale, Rv.y, scale * X.y);
-            if (a == 0) X = make_float2(0.f, 0.f);
-          }
-          dst[a] = X;
+        uint32_t o;
+        if constexpr (CACHE) o = at[q][k1]; else o = store_offset(q, k1);
+        float2 X = w[bitrev<P1>(k1)];
+        if constexpr (!REF) {
+          X.x *= scale;
+          X.y *= scale;
         }
+        // Only output (q, k1) = (0, 0) of thread 0 of group 0 is k = 0.
+        if constexpr (q == 0 && k1 == 0) {
+          if (o == 0) X = make_float2(0.f, 0.f);
+        }
+        buffer_store(X, dst, o);
       });
     });
+    if (++slot == capacity) slot = 0;
     __syncthreads();  // LDS is rewritten by the next frame
   }
 }
@@ -442,7 +449,7 @@ hipError_t row_dispatch(int in_dtype, const void* frames, const void* ref, const
 
 template <int N>
 hipError_t col_launch(bool reference, const float2* inter, const double* rowsum, int nframes,
-                      int64_t t0, int64_t capacity, int64_t mode_stride,
+                      int64_t t0, int64_t capacity, int64_t mode_stride, int64_t n_modes,
                       const int32_t* row_width, const int32_t* row_offset, const float2* tw,
                       float2* ring, float2* refspec, double* refscal, float2* fscale,
                       int32_t* status, hipStream_t s) {
@@ -451,16 +458,16 @@ hipError_t col_launch(bool reference, const float2* inter, const double* rowsum,
   const int64_t blocks = int64_t(C::GROUPS) * ((nframes + per - 1) / per);
   if (reference) {
     hipLaunchKernelGGL(frame_scale_kernel<true>, dim3(unsigned(nframes)), dim3(256), 0, s, N,
-                       rowsum, refscal, fscale, status);
+                       rowsum, refscal, fscale, t0, capacity, status);
     hipLaunchKernelGGL((col_pass_kernel<N, true>), dim3(unsigned(blocks)), dim3(C::THREADS), 0,
-                       s, inter, fscale, nframes, per, t0, capacity, mode_stride, row_width,
-                       row_offset, tw, ring, refspec);
+                       s, inter, fscale, nframes, per, t0, capacity, mode_stride, n_modes,
+                       row_width, row_offset, tw, ring, refspec);
   } else {
     hipLaunchKernelGGL(frame_scale_kernel<false>, dim3(unsigned(nframes)), dim3(256), 0, s, N,
-                       rowsum, refscal, fscale, status);
+                       rowsum, refscal, fscale, t0, capacity, status);
     hipLaunchKernelGGL((col_pass_kernel<N, false>), dim3(unsigned(blocks)), dim3(C::THREADS), 0,
-                       s, inter, fscale, nframes, per, t0, capacity, mode_stride, row_width,
-                       row_offset, tw, ring, refspec);
+                       s, inter, fscale, nframes, per, t0, capacity, mode_stride, n_modes,
+                       row_width, row_offset, tw, ring, refspec);
   }
   return hipGetLastError();
 }
@@ -490,14 +497,14 @@ hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* 
 
 hipError_t launch_col_pass(int n, bool reference, const float2* inter, const double* rowsum,
                            int nframes, int64_t t0, int64_t capacity, int64_t mode_stride,
-                           const int32_t* row_width, const int32_t* row_offset,
+                           int64_t n_modes, const int32_t* row_width, const int32_t* row_offset,
                            const float2* tw, float2* ring, float2* refspec, double* refscal,
                            float2* fscale, int32_t* status, hipStream_t s) {
-#define NFS_COL_CASE(NN)                                                                   \
-  case NN:                                                                                 \
-    return col_launch<NN>(reference, inter, rowsum, nframes, t0, capacity, mode_stride,   \
-                          row_width, row_offset, tw, ring, refspec, refscal, fscale, status, \
-                          s);
+#define NFS_COL_CASE(NN)                                                                  \
+  case NN:                                                                                \
+    return col_launch<NN>(reference, inter, rowsum, nframes, t0, capacity, mode_stride,  \
+                          n_modes, row_width, row_offset, tw, ring, refspec, refscal,    \
+                          fscale, status, s);
   switch (n) {
     NFS_COL_CASE(16)
     NFS_COL_CASE(32)

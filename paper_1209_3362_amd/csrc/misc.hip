@@ -24,14 +24,16 @@ __global__ void bin_map_kernel(int n, int nb, int32_t* __restrict__ map) {
   }
 }
 
+// I_t = stored value + sigma_t * F[reference] on the stored modes,
+// I_t(0) = n^2, zero elsewhere.
 __global__ void expand_kernel(int n, const float2* __restrict__ spec,
                               const int32_t* __restrict__ row_width,
                               const int32_t* __restrict__ row_offset,
                               const float2* __restrict__ refspec,
-                              const double* __restrict__ refscal, float2* __restrict__ out) {
+                              const float2* __restrict__ fscale_slot, float2* __restrict__ out) {
   const int h = n / 2;
   const int64_t total = int64_t(n) * h;
-  const float sref = float(refscal[1]);
+  const float sigma = fscale_slot->x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int r = int(i / h), kx = int(i % h);
@@ -39,7 +41,7 @@ __global__ void expand_kernel(int n, const float2* __restrict__ spec,
     if (kx < row_width[r]) {
       const int64_t at = row_offset[r] + kx;
       const float2 a = spec[at], R = refspec[at];
-      v = make_float2(fmaf(sref, R.x, a.x), fmaf(sref, R.y, a.y));
+      v = make_float2(fmaf(sigma, R.x, a.x), fmaf(sigma, R.y, a.y));
       if (at == 0) v = make_float2(float(n) * float(n), 0.f);
     }
     out[i] = v;
@@ -70,10 +72,11 @@ hipError_t launch_bin_map(int n, int n_bins, int32_t* map, hipStream_t s) {
 
 hipError_t launch_expand_spectrum(int n, const float2* ring, int64_t slot, int64_t mode_stride,
                                   const int32_t* row_width, const int32_t* row_offset,
-                                  const float2* refspec, const double* refscal, float2* out,
+                                  const float2* refspec, const float2* fscale, float2* out,
                                   hipStream_t s) {
   hipLaunchKernelGGL(expand_kernel, dim3(grid_for(int64_t(n) * (n / 2), 256)), dim3(256), 0, s,
-                     n, ring + slot * mode_stride, row_width, row_offset, refspec, refscal, out);
+                     n, ring + slot * mode_stride, row_width, row_offset, refspec, fscale + slot,
+                     out);
   return hipGetLastError();
 }
 

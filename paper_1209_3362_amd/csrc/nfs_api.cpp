@@ -33,7 +33,7 @@ struct nfs_plan_s {
   double* refscal = nullptr;    // {S_ref, sigma_ref} of the reference frame
   void* ref = nullptr;          // reference frame: first frame of the sequence
   float2* refspec = nullptr;    // its transform on the stored modes
-  float2* fscale = nullptr;     // per-frame scales of the current batch
+  float2* fscale = nullptr;     // per ring slot: {sigma, sigma - sigma_ref}
   int32_t* seg_bin = nullptr;   // binning segments (see nfs::Layout)
   int32_t* seg_row0 = nullptr;
   int32_t* bin_seg0 = nullptr;
@@ -75,7 +75,8 @@ nfs_status flush_pairs(nfs_plan_s* h) {
   if (h->t_done >= h->t_pushed) return NFS_OK;
   const nfs::Layout& L = h->L;
   for (const nfs::LagGroup& g : L.groups) {
-    hipError_t e = nfs::launch_pairs(h->ring, L.modes, L.mode_stride, L.capacity, h->t_done,
+    hipError_t e = nfs::launch_pairs(h->ring, h->refspec, h->fscale, L.modes, L.mode_stride,
+                                     L.capacity, h->t_done,
                                      h->t_pushed, h->lags + g.first, g.count, g.max_lag,
                                      h->acc + g.first, L.n_lags, g.modes, g.hist, g.waves,
                                      g.per_wave, g.lds, h->stream);
@@ -186,6 +187,10 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->bin_seg0, L.bin_seg0.data(), L.bin_seg0.size() * 4,
                        hipMemcpyHostToDevice, h->stream);
+  // The pair kernel reads the reference transform in whole workgroup tiles
+  // of modes, up to mode_stride; entries past the stored modes stay zero.
+  if (e == hipSuccess)
+    e = nfs::launch_fill_u32(h->refspec, size_t(L.mode_stride) * 2, 0u, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     delete h;
@@ -239,7 +244,7 @@ nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count) {
                                h->rowsum, h->tw, h->stream);
       if (e == hipSuccess)
         e = nfs::launch_col_pass(L.n, true, h->inter, h->rowsum, 1, 0, L.capacity,
-                                 L.mode_stride, h->width, h->offset, h->tw, h->ring,
+                                 L.mode_stride, L.modes, h->width, h->offset, h->tw, h->ring,
                                  h->refspec, h->refscal, h->fscale, h->status, h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "reference transform launch");
     }
@@ -247,8 +252,8 @@ nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count) {
                              h->rowsum, h->tw, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
     e = nfs::launch_col_pass(L.n, false, h->inter, h->rowsum, int(b), h->t_pushed, L.capacity,
-                             L.mode_stride, h->width, h->offset, h->tw, h->ring, h->refspec,
-                             h->refscal, h->fscale, h->status, h->stream);
+                             L.mode_stride, L.modes, h->width, h->offset, h->tw, h->ring,
+                             h->refspec, h->refscal, h->fscale, h->status, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
     h->t_pushed += b;
     i += b;
@@ -317,7 +322,7 @@ nfs_status nfs_copy_spectrum(nfs_handle h, int64_t t, float* out) {
     return fail(h, NFS_E_STATE, "frame is not in the ring");
   hipError_t e = nfs::launch_expand_spectrum(h->L.n, h->ring, t % h->L.capacity,
                                              h->L.mode_stride, h->width, h->offset, h->refspec,
-                                             h->refscal, reinterpret_cast<float2*>(out),
+                                             h->fscale, reinterpret_cast<float2*>(out),
                                              h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "expand launch");
   return NFS_OK;

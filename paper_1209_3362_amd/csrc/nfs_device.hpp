@@ -23,6 +23,27 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 w) {
 }
 
 // ---------------------------------------------------------------------------
+// Raw buffer stores: a buffer resource covers `bytes` bytes from its base;
+// the hardware drops a store whose byte offset lies at or past that range,
+// so kDropOffset marks an element that is not written, without a branch.
+using BufferRsrc = __amdgpu_buffer_rsrc_t;
+constexpr uint32_t kDropOffset = 0x80000000u;
+// Word 3 of a gfx9 buffer descriptor: 32-bit data format, no swizzle.
+constexpr int kBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ BufferRsrc make_buffer(void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(base, static_cast<short>(0), static_cast<int>(bytes),
+                                           kBufferWord3);
+}
+__device__ __forceinline__ void buffer_store(float2 v, BufferRsrc r, uint32_t byte_offset) {
+  using U2 = __attribute__((ext_vector_type(2))) unsigned;
+  U2 bits;
+  bits.x = __float_as_uint(v.x);
+  bits.y = __float_as_uint(v.y);
+  __builtin_amdgcn_raw_buffer_store_b64(bits, r, static_cast<int>(byte_offset), 0, 0);
+}
+
+// ---------------------------------------------------------------------------
 // Compile-time cos/sin of 2*pi*j/n, evaluated in double: the angle is split
 // into its octant and a remainder in [0, pi/4], where Taylor series converge
 // to double precision in 14 terms; results are exact at multiples of pi/2.

@@ -64,6 +64,17 @@ nfs_status validate_desc(const nfs_desc* d, std::string* err) {
   return NFS_OK;
 }
 
+int pair_simd_load(int count, int waves) {
+  const int base = count / waves, extra = count % waves;
+  int worst = 0;
+  for (int simd = 0; simd < 4; ++simd) {
+    int load = 0;
+    for (int w = simd; w < waves; w += 4) load += base + (w < extra ? 1 : 0);
+    worst = std::max(worst, load);
+  }
+  return worst;
+}
+
 static bool plan_group(const std::vector<int32_t>& lags, int first, int count,
                        LagGroup* g) {
   g->first = first;
@@ -82,15 +93,17 @@ static bool plan_group(const std::vector<int32_t>& lags, int first, int count,
     }
   }
   if (!g->modes) return false;
-  // Wave w takes lags [w * per_wave, (w + 1) * per_wave): pick the wave
-  // count with the fewest unused slots, ties to more waves.
-  int best_w = 0, best_waste = std::numeric_limits<int>::max();
+  // The lags are split over W waves in contiguous slices whose lengths
+  // differ by at most one; waves w, w + 4, w + 8 share a SIMD, so pick the
+  // W whose busiest SIMD has the fewest lags, ties to fewer waves (more
+  // lags per wave share each chunk's target loads).
+  int best_w = 0, best_cost = std::numeric_limits<int>::max();
   for (int W = 1; W <= kMaxPairWaves; ++W) {
     const int per = (count + W - 1) / W;
-    if (per > kMaxLagsPerWave || (W - 1) * per >= count) continue;
-    const int waste = per * W - count;
-    if (waste <= best_waste) {
-      best_waste = waste;
+    if (per > kMaxLagsPerWave) continue;
+    const int cost = pair_simd_load(count, W);
+    if (cost < best_cost) {
+      best_cost = cost;
       best_w = W;
     }
   }
@@ -180,18 +193,20 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_lags = take(size_t(o.n_lags) * 4);
   o.off_ref = take(size_t(o.n) * o.n * (o.in_dtype == NFS_IN_U16 ? 2 : 4));
   o.off_refspec = take(size_t(o.mode_stride) * 8);
-  o.off_fscale = take(size_t(o.batch) * 8);
   o.off_ring = off;
+  // Each ring slot holds one spectrum and, after the ring, its frame's
+  // scales; spectra are whole multiples of kAlign bytes.
   const size_t spec_bytes = size_t(o.mode_stride) * 8;
+  const size_t slot_bytes = spec_bytes + 8;
 
   if (d->capacity > 0) {
     o.capacity = d->capacity;
   } else if (bytes_available > 0) {
-    if (bytes_available <= o.off_ring) {
+    if (bytes_available <= o.off_ring + kAlign) {
       if (err) *err = "workspace too small for any spectrum ring";
       return NFS_E_WORKSPACE;
     }
-    o.capacity = int64_t((bytes_available - o.off_ring) / spec_bytes);
+    o.capacity = int64_t((bytes_available - o.off_ring - kAlign) / slot_bytes);
   } else {
     o.capacity = int64_t(o.max_lag) + 64;
   }
@@ -199,7 +214,8 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
     if (err) *err = "ring capacity must exceed the largest lag";
     return NFS_E_CAPACITY;
   }
-  o.total = align_up(o.off_ring + size_t(o.capacity) * spec_bytes, kAlign);
+  o.off_fscale = o.off_ring + size_t(o.capacity) * spec_bytes;
+  o.total = align_up(o.off_fscale + size_t(o.capacity) * 8, kAlign);
   return NFS_OK;
 }
 

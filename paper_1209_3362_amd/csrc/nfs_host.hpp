@@ -49,14 +49,19 @@ int bin_of(int n, int nb, int ky, int kx);
 void ring_bounds(int n, int nb, int b, int64_t* lo, int64_t* hi);
 
 // One group of lags handled by one launch of the pair kernel.
+// Lags of the busiest SIMD when `count` lags are split over `waves` waves
+// in contiguous slices whose lengths differ by at most one (the first
+// count % waves waves take one more) and wave w runs on SIMD w % 4.
+int pair_simd_load(int count, int waves);
+
 struct LagGroup {
   int first = 0;      // index of the group's first lag in the lag list
   int count = 0;      // lags in the group
   int max_lag = 0;    // largest lag of the group
   int modes = 0;      // K: modes per workgroup
   int hist = 0;       // H: history rows kept in LDS (multiple of the chunk)
-  int waves = 0;      // waves per workgroup
-  int per_wave = 0;   // lags per wave (<= kMaxLagsPerWave)
+  int waves = 0;      // waves that sum lags (the launch has at least 4)
+  int per_wave = 0;   // most lags of one wave (<= kMaxLagsPerWave)
   size_t lds = 0;     // dynamic LDS bytes
 };
 
@@ -80,7 +85,7 @@ struct Layout {
   size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_acc = 0;
   size_t off_status = 0, off_tw = 0, off_width = 0, off_offset = 0;
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
-  size_t off_fscale = 0;                // per-frame {sigma, sigma - sigma_ref}
+  size_t off_fscale = 0;  // after the ring: per slot {sigma, sigma - sigma_ref}
   size_t off_segs = 0, off_part = 0, off_part_cnt = 0;
   size_t off_lags = 0, total = 0;
 };

@@ -21,25 +21,28 @@ hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* 
 // Frame scales from the row sums, then the column pass (per column k_x:
 // complex transform over the n rows).
 // reference == true: the rows are the reference image (one frame); store its
-// transform unscaled in refspec and refscal = {S_ref, n^2/S_ref}.
+// transform unscaled in refspec (0 at k = 0) and refscal = {S_ref, n^2/S_ref}.
 // reference == false: the rows are (frame - reference); with
-// sigma = n^2 / (S_ref + row sums), fscale[f] = {sigma, sigma - sigma_ref},
-// store sigma * X + (sigma - sigma_ref) * refspec, 0 at k = 0, for frame f
-// into ring slot (t0 + f) mod capacity. A frame whose sum is not positive
-// and finite sets bit 0 of *status and gets sigma = 0.
+// sigma = n^2 / (S_ref + row sums), fscale[slot] = {sigma, sigma - sigma_ref}
+// and sigma * X, 0 at k = 0, stored for frame f in ring slot
+// slot = (t0 + f) mod capacity. A frame whose sum is not positive and finite
+// sets bit 0 of *status and gets sigma = 0. n_modes: stored modes per
+// spectrum; only those are written.
 hipError_t launch_col_pass(int n, bool reference, const float2* inter, const double* rowsum,
                            int nframes, int64_t t0, int64_t capacity, int64_t mode_stride,
-                           const int32_t* row_width, const int32_t* row_offset,
+                           int64_t n_modes, const int32_t* row_width, const int32_t* row_offset,
                            const float2* tw, float2* ring, float2* refspec, double* refscal,
                            float2* fscale, int32_t* status, hipStream_t s);
 
 // Lag-pair accumulation for target frames [T0, T1) and the lags
 // lags[0..n_lags): acc[m * acc_pitch + l] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2
-// over t in [T0, T1) with t - lag >= 0 (acc is mode-major). Frames
-// [max(0, T0 - max lag), T1) must be in the ring. `modes` per workgroup
-// (64, 32, 16 or 8), `hist` LDS rows; wave w sums lags
-// [w * per_wave, (w + 1) * per_wave) (per_wave <= kMaxLagsPerWave).
-hipError_t launch_pairs(const float2* ring, int64_t n_modes, int64_t mode_stride,
+// over t in [T0, T1) with t - lag >= 0 (acc is mode-major), where
+// I_t = ring slot of t + fscale[slot].y * refspec (refspec has mode_stride
+// entries, 0 at k = 0). Frames [max(0, T0 - max lag), T1) must be in the
+// ring. `modes` per workgroup (64, 32, 16 or 8), `hist` LDS rows; wave w
+// sums lags [w * per_wave, (w + 1) * per_wave) (per_wave <= kMaxLagsPerWave).
+hipError_t launch_pairs(const float2* ring, const float2* refspec, const float2* fscale,
+                        int64_t n_modes, int64_t mode_stride,
                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                         int n_lags, int max_lag, float* acc, int acc_pitch, int modes, int hist,
                         int waves, int per_wave, size_t lds, hipStream_t s);
@@ -63,10 +66,11 @@ hipError_t launch_fill_u32(void* dst, size_t words, uint32_t value, hipStream_t 
 hipError_t launch_bin_map(int n, int n_bins, int32_t* map, hipStream_t s);
 
 // Expands ring slot `slot` to the spectrum out [n][n/2] complex: stored
-// value + sigma_ref * refspec, I(0) = n^2, zeros where not stored.
+// value + sigma * refspec (sigma = fscale[slot].x), I(0) = n^2, zeros where
+// not stored.
 hipError_t launch_expand_spectrum(int n, const float2* ring, int64_t slot,
                                   int64_t mode_stride, const int32_t* row_width,
                                   const int32_t* row_offset, const float2* refspec,
-                                  const double* refscal, float2* out, hipStream_t s);
+                                  const float2* fscale, float2* out, hipStream_t s);
 
 }  // namespace nfs

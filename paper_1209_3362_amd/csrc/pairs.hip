@@ -13,6 +13,12 @@
 // wave whose lags are consecutive integers reads one register window of
 // older frames shared by all its lags instead. The first rows of the LDS
 // ring are mirrored after its end so a lane's run of rows never wraps.
+//
+// A ring slot holds sigma_t F[frame_t - reference]; the spectrum the pairs
+// use is that plus (sigma_t - sigma_ref) F[reference], i.e. the normalised
+// transform minus the constant sigma_ref F[reference], which cancels in
+// every difference. The correction is applied once per (frame, mode) as the
+// slot is copied into LDS.
 #include "nfs_device.hpp"
 #include "nfs_host.hpp"
 #include "nfs_kernels.hpp"
@@ -20,14 +26,15 @@
 namespace nfs {
 namespace {
 
-// K modes per workgroup, MAXLW lag slots per wave (the wave's lags are the
-// contiguous slice [wave * MAXLW, wave * MAXLW + MAXLW) of the list; slots
-// past its end read harmless rows and are not summed).
+// K modes per workgroup, MAXLW lag slots per wave: the lag list is split
+// into lag_waves contiguous slices of near-equal length, one per wave;
+// slots past a slice's end read harmless rows and are not summed.
 template <int K, int MAXLW>
 __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
-    const float2* __restrict__ ring, int64_t n_modes, int64_t mode_stride, int64_t capacity,
+    const float2* __restrict__ ring, const float2* __restrict__ refspec,
+    const float2* __restrict__ fscale, int64_t n_modes, int64_t mode_stride, int64_t capacity,
     int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags, int max_lag,
-    float* __restrict__ acc, int acc_pitch, int H) {
+    float* __restrict__ acc, int acc_pitch, int H, int lag_waves) {
   constexpr int S = pair_chunk(K);  // frames per chunk
   constexpr int G = 64 / K;         // lanes sharing one mode inside a wave
   constexpr int RPT = S / G;        // target rows per lane per chunk
@@ -47,10 +54,13 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
   const int64_t m0 = int64_t(blockIdx.x) * K;
   const int len = int(T1 - T0);  // frames in this window (< capacity)
 
-  // This wave's lags, in scalar registers. A target frame at window offset
-  // u has a partner for lag tau[s] iff u >= first[s].
-  const int l_begin = wave * MAXLW;
-  const int l_count = max(0, min(MAXLW, n_lags - l_begin));
+  // This wave's lags, in scalar registers: the first n_lags % lag_waves
+  // waves take one lag more than the others (waves past lag_waves none). A
+  // target frame at window offset u has a partner for lag tau[s] iff
+  // u >= first[s].
+  const int base = n_lags / lag_waves, extra = n_lags % lag_waves;
+  const int l_begin = wave * base + min(wave, extra);
+  const int l_count = wave < lag_waves ? base + (wave < extra ? 1 : 0) : 0;
   int tau[MAXLW], first[MAXLW];
 #pragma unroll
   for (int s = 0; s < MAXLW; ++s) {
@@ -73,32 +83,49 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
     hist4[(row * K) / 2 + col2] = val;
     if (row < MR) hist4[((row + H) * K) / 2 + col2] = val;
   };
+  // Slot value v of two modes plus d * F[reference] of the same modes.
+  const float4* ref4 = reinterpret_cast<const float4*>(refspec + m0);
+  auto corrected = [](float4 v, float d, float4 R) {
+    return make_float4(fmaf(d, R.x, v.x), fmaf(d, R.y, v.y), fmaf(d, R.z, v.z),
+                       fmaf(d, R.w, v.w));
+  };
 
   // History from earlier windows: frames [max(0, T0 - max_lag), T0).
   {
     const int pre = int(T0 - max_lag > 0 ? max_lag : T0);
     int64_t slot = (T0 - pre) % capacity;
     for (int r = 0; r < pre; ++r) {
+      const float d = fscale[slot].y;
       for (int col2 = threadIdx.x; col2 < V4; col2 += nthreads)
-        put_row((max_lag - pre + r) % H, col2, slot_row(slot)[col2]);
+        put_row((max_lag - pre + r) % H, col2, corrected(slot_row(slot)[col2], d, ref4[col2]));
       if (++slot == capacity) slot = 0;
     }
   }
 
-  float4 pf[MAXPF];
+  // Each thread copies the same two modes of every chunk row it handles, so
+  // their reference values stay in registers.
+  float4 pf[MAXPF], rr[MAXPF];
+  float pd[MAXPF];
   const int n_el = S * V4;  // float4 per chunk
+#pragma unroll
+  for (int i = 0; i < MAXPF; ++i) {
+    const int e = threadIdx.x + i * nthreads;
+    rr[i] = e < n_el ? ref4[e % V4] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   // Chunk at window offset c starts in ring slot cslot; slots wrap once.
   auto prefetch = [&](int c, int64_t cslot) {
 #pragma unroll
     for (int i = 0; i < MAXPF; ++i) {
       const int e = threadIdx.x + i * nthreads;
       pf[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+      pd[i] = 0.f;
       if (e < n_el) {
         const int dt = e / V4;
         if (c + dt < len) {
           int64_t slot = cslot + dt;
           if (slot >= capacity) slot -= capacity;
           pf[i] = slot_row(slot)[e % V4];
+          pd[i] = fscale[slot].y;
         }
       }
     }
@@ -110,7 +137,7 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
       if (e < n_el) {
         int row = crow + e / V4;
         if (row >= H) row -= H;
-        put_row(row, e % V4, pf[i]);
+        put_row(row, e % V4, corrected(pf[i], pd[i], rr[i]));
       }
     }
   };
@@ -175,50 +202,41 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
 #pragma unroll
       for (int i = 0; i < RPT; ++i) o[i] = src[i * K];
     };
-    if (full && c >= first_max) {
-      // Every target of the chunk has a partner for every lag of the wave.
-      if (consecutive) {
-        // Rows rb - tau[0] - (MAXLW-1) .. rb - tau[0] + RPT - 1 serve every
-        // lag of the run: lag tau[0] + s reads win[MAXLW - 1 - s + i].
-        float2 win[WIN];
-        const float2* src = older(tau[0] + MAXLW - 1);
+    if (consecutive && full && c >= first_max) {
+      // Every target of the chunk has a partner for every lag of the run:
+      // rows rb - tau[0] - (MAXLW-1) .. rb - tau[0] + RPT - 1 serve them
+      // all, lag tau[0] + s reads win[MAXLW - 1 - s + i].
+      float2 win[WIN];
+      const float2* src = older(tau[0] + MAXLW - 1);
 #pragma unroll
-        for (int i = 0; i < WIN; ++i) win[i] = src[i * K];
-        dev::static_for<MAXLW>([&](auto SS) {
-          constexpr int s = decltype(SS)::value;
-          if (s < l_count) acc_plain(cur, win + (MAXLW - 1 - s), s);
-        });
-      } else {
-        // The older rows of slot s+1 are read while slot s is summed.
-        float2 o0[RPT], o1[RPT];
-        load_old(o0, tau[0]);
-        dev::static_for<MAXLW>([&](auto SS) {
-          constexpr int s = decltype(SS)::value;
-          constexpr int nx = s + 1 < MAXLW ? s + 1 : s;
-          if constexpr ((s & 1) == 0) {
-            if constexpr (s + 1 < MAXLW) load_old(o1, tau[nx]);
-            if (s < l_count) acc_plain(cur, o0, s);
-          } else {
-            if constexpr (s + 1 < MAXLW) load_old(o0, tau[nx]);
-            if (s < l_count) acc_plain(cur, o1, s);
-          }
-        });
-      }
+      for (int i = 0; i < WIN; ++i) win[i] = src[i * K];
+      dev::static_for<MAXLW>([&](auto SS) {
+        constexpr int s = decltype(SS)::value;
+        if (s < l_count) acc_plain(cur, win + (MAXLW - 1 - s), s);
+      });
     } else {
-      // Early chunks (some targets precede their partner) and the window's
-      // last, partial chunk.
+      // Per lag slot (wave-uniform): every target of the chunk has a
+      // partner (plain sums), some do (masked sums) or none (skipped). The
+      // older rows of slot s+1 are read while slot s is summed.
+      auto sum_slot = [&](const float2* o, int s) {
+        if (s < l_count) {
+          if (full && c >= first[s])
+            acc_plain(cur, o, s);
+          else if (c + S > first[s])
+            acc_masked(cur, o, s, ub);
+        }
+      };
       float2 o0[RPT], o1[RPT];
       load_old(o0, tau[0]);
       dev::static_for<MAXLW>([&](auto SS) {
         constexpr int s = decltype(SS)::value;
         constexpr int nx = s + 1 < MAXLW ? s + 1 : s;
-        const bool act = s < l_count && c + S > first[s];
         if constexpr ((s & 1) == 0) {
           if constexpr (s + 1 < MAXLW) load_old(o1, tau[nx]);
-          if (act) acc_masked(cur, o0, s, ub);
+          sum_slot(o0, s);
         } else {
           if constexpr (s + 1 < MAXLW) load_old(o0, tau[nx]);
-          if (act) acc_masked(cur, o1, s, ub);
+          sum_slot(o1, s);
         }
       });
     }
@@ -250,7 +268,8 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
 }
 
 template <int K, int P>
-hipError_t pair_launch(const float2* ring, int64_t n_modes, int64_t mode_stride,
+hipError_t pair_launch(const float2* ring, const float2* refspec, const float2* fscale,
+                       int64_t n_modes, int64_t mode_stride,
                        int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                        int n_lags, int max_lag, float* acc, int acc_pitch, int hist, int waves,
                        size_t lds, hipStream_t s) {
@@ -261,20 +280,22 @@ hipError_t pair_launch(const float2* ring, int64_t n_modes, int64_t mode_stride,
   const int64_t blocks = (n_modes + K - 1) / K;
   const int launched = waves < 4 ? 4 : waves;  // extra waves only help load
   hipLaunchKernelGGL((pair_kernel<K, P>), dim3(unsigned(blocks)), dim3(64 * launched), lds, s,
-                     ring, n_modes, mode_stride, capacity, T0, T1, lags, n_lags, max_lag, acc,
-                     acc_pitch, hist);
+                     ring, refspec, fscale, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,
+                     max_lag, acc, acc_pitch, hist, waves);
   return hipGetLastError();
 }
 
 template <int K>
-hipError_t pair_dispatch(int per_wave, const float2* ring, int64_t n_modes,
+hipError_t pair_dispatch(int per_wave, const float2* ring, const float2* refspec,
+                         const float2* fscale, int64_t n_modes,
                          int64_t mode_stride, int64_t capacity, int64_t T0, int64_t T1,
                          const int32_t* lags, int n_lags, int max_lag, float* acc,
                          int acc_pitch, int hist, int waves, size_t lds, hipStream_t s) {
 #define NFS_PAIR_P(PP)                                                                     \
   case PP:                                                                                 \
-    return pair_launch<K, PP>(ring, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,  \
-                              max_lag, acc, acc_pitch, hist, waves, lds, s);
+    return pair_launch<K, PP>(ring, refspec, fscale, n_modes, mode_stride, capacity, T0,  \
+                              T1, lags, n_lags, max_lag, acc, acc_pitch, hist, waves, lds, \
+                              s);
   switch (per_wave) {
     NFS_PAIR_P(1)
     NFS_PAIR_P(2)
@@ -291,14 +312,16 @@ hipError_t pair_dispatch(int per_wave, const float2* ring, int64_t n_modes,
 
 }  // namespace
 
-hipError_t launch_pairs(const float2* ring, int64_t n_modes, int64_t mode_stride,
+hipError_t launch_pairs(const float2* ring, const float2* refspec, const float2* fscale,
+                        int64_t n_modes, int64_t mode_stride,
                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                         int n_lags, int max_lag, float* acc, int acc_pitch, int modes, int hist,
                         int waves, int per_wave, size_t lds, hipStream_t s) {
 #define NFS_PAIR_CASE(KK)                                                                  \
   case KK:                                                                                 \
-    return pair_dispatch<KK>(per_wave, ring, n_modes, mode_stride, capacity, T0, T1, lags, \
-                             n_lags, max_lag, acc, acc_pitch, hist, waves, lds, s);
+    return pair_dispatch<KK>(per_wave, ring, refspec, fscale, n_modes, mode_stride,        \
+                             capacity, T0, T1, lags, n_lags, max_lag, acc, acc_pitch, hist, \
+                             waves, lds, s);
   switch (modes) {
     NFS_PAIR_CASE(64)
     NFS_PAIR_CASE(32)
