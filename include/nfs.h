@@ -57,7 +57,8 @@ typedef enum {
                                  kernel's on-chip history can hold (2400)    */
   NFS_E_BINS = 4,             /* n_bins outside [1, n/2]                     */
   NFS_E_WORKSPACE = 5,        /* workspace null, misaligned or too small     */
-  NFS_E_CAPACITY = 6,         /* ring capacity not larger than the max lag   */
+  NFS_E_CAPACITY = 6,         /* ring capacity negative, not larger than the
+                                 max lag, or 2^31 or more                    */
   NFS_E_STATE = 7,            /* handle destroyed or used out of order       */
   NFS_E_DEGENERATE_FRAME = 8, /* a frame had a non-positive spatial sum      */
   NFS_E_HIP = 9,              /* a HIP runtime call failed                   */
@@ -85,7 +86,8 @@ typedef struct {
                            log-spaced ones (discussion section)              */
   int32_t n_bins;       /* number of |q| rings, 1 .. n/2                      */
   int64_t capacity;     /* spectra kept resident (ring slots); must exceed the
-                           largest lag; 0 = as many as the workspace holds    */
+                           largest lag and be below 2^31; 0 = as many as the
+                           workspace holds (at most 2^31 - 1)                 */
   const float* window;  /* device [n][n] per-pixel weight multiplied into
                            every frame before normalisation, or NULL;
                            borrowed: must stay valid while the plan is used   */

@@ -59,6 +59,7 @@ nfs_status validate_desc(const nfs_desc* d, std::string* err) {
   if (d->n_bins < 1 || d->n_bins > d->n / 2)
     return fail(NFS_E_BINS, "n_bins must be in [1, n/2]");
   if (d->capacity < 0) return fail(NFS_E_CAPACITY, "capacity must be >= 0");
+  if (d->capacity > kMaxCapacity) return fail(NFS_E_CAPACITY, "capacity must be < 2^31");
   if (d->capacity > 0 && d->capacity <= d->lags[d->n_lags - 1])
     return fail(NFS_E_CAPACITY, "capacity must exceed the largest lag");
   return NFS_OK;
@@ -101,6 +102,8 @@ static bool plan_group(const std::vector<int32_t>& lags, int first, int count,
   for (int W = 1; W <= kMaxPairWaves; ++W) {
     const int per = (count + W - 1) / W;
     if (per > kMaxLagsPerWave) continue;
+    // Workgroups of 12 waves are built for 6 or more lags per wave only.
+    if (W > 8 && per < 6) continue;
     const int cost = pair_simd_load(count, W);
     if (cost < best_cost) {
       best_cost = cost;
@@ -206,7 +209,8 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
       if (err) *err = "workspace too small for any spectrum ring";
       return NFS_E_WORKSPACE;
     }
-    o.capacity = int64_t((bytes_available - o.off_ring - kAlign) / slot_bytes);
+    o.capacity = std::min<int64_t>(kMaxCapacity,
+                                   int64_t((bytes_available - o.off_ring - kAlign) / slot_bytes));
   } else {
     o.capacity = int64_t(o.max_lag) + 64;
   }

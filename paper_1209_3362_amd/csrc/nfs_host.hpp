@@ -22,8 +22,8 @@ constexpr int pair_chunk(int K) { return K == 64 ? 16 : 32; }
 // per workgroup; a launch handles at most their product.
 constexpr int kMaxLagsPerWave = 8;
 constexpr int kMaxPairWaves = 12;
-// LDS rows mirrored after the pair kernel's history ring: a lane reads at
-// most max(S, S*K/64 + kMaxLagsPerWave - 1) consecutive rows.
+// LDS rows mirrored after the pair kernel's history ring: from a row of the
+// ring a lane reads up to S + kMaxLagsPerWave - 2 rows further on.
 constexpr int pair_mirror(int K) { return pair_chunk(K) + kMaxLagsPerWave; }
 // LDS a workgroup may allocate on gfx950.
 constexpr int kLdsBytes = 160 * 1024;
@@ -34,6 +34,8 @@ constexpr int kSegRows = 64;
 // Target size of the row-transform intermediate of one batch of frames.
 constexpr size_t kBatchBytes = size_t(128) << 20;
 constexpr int kMaxBatch = 1024;
+// Most ring slots (slot indices are 32-bit in the kernels).
+constexpr int64_t kMaxCapacity = 0x7fffffff;
 
 inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -60,7 +62,7 @@ struct LagGroup {
   int max_lag = 0;    // largest lag of the group
   int modes = 0;      // K: modes per workgroup
   int hist = 0;       // H: history rows kept in LDS (multiple of the chunk)
-  int waves = 0;      // waves that sum lags (the launch has at least 4)
+  int waves = 0;      // waves that sum lags (the launch has 8, or 12 if more)
   int per_wave = 0;   // most lags of one wave (<= kMaxLagsPerWave)
   size_t lds = 0;     // dynamic LDS bytes
 };

@@ -26,11 +26,12 @@
 namespace nfs {
 namespace {
 
-// K modes per workgroup, MAXLW lag slots per wave: the lag list is split
-// into lag_waves contiguous slices of near-equal length, one per wave;
-// slots past a slice's end read harmless rows and are not summed.
-template <int K, int MAXLW>
-__global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
+// K modes per workgroup, MAXLW lag slots per wave, NW waves launched: the
+// lag list is split into lag_waves <= NW contiguous slices of near-equal
+// length, one per wave; slots past a slice's end read harmless rows and are
+// not summed. NW = 8 leaves each wave 256 registers, NW = 12 170.
+template <int K, int MAXLW, int NW>
+__global__ __launch_bounds__(64 * NW) void pair_kernel(
     const float2* __restrict__ ring, const float2* __restrict__ refspec,
     const float2* __restrict__ fscale, int64_t n_modes, int64_t mode_stride, int64_t capacity,
     int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags, int max_lag,
@@ -39,11 +40,12 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
   constexpr int G = 64 / K;         // lanes sharing one mode inside a wave
   constexpr int RPT = S / G;        // target rows per lane per chunk
   constexpr int V4 = K / 2;         // float4 (two modes) per ring row of the tile
-  constexpr int WIN = RPT + MAXLW - 1;  // register window of a run of consecutive lags
   constexpr int MR = pair_mirror(K);    // rows mirrored past the end of the LDS ring
-  static_assert(MR >= S && MR >= WIN - 1, "mirror too short for a lane's row run");
-  // float4 per thread per chunk; launches have at least 4 waves.
-  constexpr int MAXPF = (S * V4 / 256) > 0 ? (S * V4 / 256) : 1;
+  // A wrapped row r < H plus a lane's run (at most S + MAXLW - 2 rows on)
+  // must stay below H + MR.
+  static_assert(MR >= S + MAXLW - 2, "mirror too short for a lane's row run");
+  // A chunk's rows are S * V4 float4: at most one per thread.
+  static_assert(S * V4 <= 64 * NW && (S * V4) % 64 == 0, "one float4 per loading thread");
   extern __shared__ float4 hist4[];
   float2* hist = reinterpret_cast<float2*>(hist4);
 
@@ -102,43 +104,37 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
     }
   }
 
-  // Each thread copies the same two modes of every chunk row it handles, so
-  // their reference values stay in registers.
-  float4 pf[MAXPF], rr[MAXPF];
-  float pd[MAXPF];
-  const int n_el = S * V4;  // float4 per chunk
-#pragma unroll
-  for (int i = 0; i < MAXPF; ++i) {
-    const int e = threadIdx.x + i * nthreads;
-    rr[i] = e < n_el ? ref4[e % V4] : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
-  // Chunk at window offset c starts in ring slot cslot; slots wrap once.
-  auto prefetch = [&](int c, int64_t cslot) {
-#pragma unroll
-    for (int i = 0; i < MAXPF; ++i) {
-      const int e = threadIdx.x + i * nthreads;
-      pf[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-      pd[i] = 0.f;
-      if (e < n_el) {
-        const int dt = e / V4;
-        if (c + dt < len) {
-          int64_t slot = cslot + dt;
-          if (slot >= capacity) slot -= capacity;
-          pf[i] = slot_row(slot)[e % V4];
-          pd[i] = fscale[slot].y;
-        }
-      }
+  // Thread e < S * V4 copies float4 column e % V4 of chunk row e / V4 (whole
+  // waves take part or not), so its two modes' reference values stay in
+  // registers. Slot arithmetic is 32-bit (capacity < 2^31).
+  const int cap = int(capacity);
+  const uint32_t stride4 = uint32_t(mode_stride / 2);  // float4 per ring slot
+  const int n_el = S * V4;
+  const bool loader = int(threadIdx.x) < n_el;
+  const int pdt = int(threadIdx.x) / V4, pcol = int(threadIdx.x) % V4;
+  const float4* pbase = reinterpret_cast<const float4*>(ring + m0) + pcol;
+  const float4 rr = loader ? ref4[pcol] : make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 pf = make_float4(0.f, 0.f, 0.f, 0.f);
+  float pd = 0.f;
+  // Rows of the chunk at window offset c, starting in ring slot cslot. A
+  // row past the window end loads the chunk's first slot instead (only
+  // masked targets ever meet it); every other row is a frame of the window
+  // (len <= capacity), so c + dt < len <= cap and one wrap of cslot + dt
+  // lands in [0, cap).
+  auto prefetch = [&](int c, int cslot) {
+    if (loader) {
+      const int dt = c + pdt < len ? pdt : 0;
+      int slot = cslot + dt;
+      if (slot >= cap) slot -= cap;
+      pf = pbase[uint64_t(uint32_t(slot)) * stride4];
+      pd = fscale[slot].y;
     }
   };
   auto commit = [&](int crow) {
-#pragma unroll
-    for (int i = 0; i < MAXPF; ++i) {
-      const int e = threadIdx.x + i * nthreads;
-      if (e < n_el) {
-        int row = crow + e / V4;
-        if (row >= H) row -= H;
-        put_row(row, e % V4, corrected(pf[i], pd[i], rr[i]));
-      }
+    if (loader) {
+      int row = crow + pdt;
+      if (row >= H) row -= H;
+      put_row(row, pcol, corrected(pf, pd, rr));
     }
   };
 
@@ -173,76 +169,140 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
   for (int s = 0; s < MAXLW; ++s)
     if (s < l_count) first_max = max(first_max, first[s]);
 
-  int crow = max_lag % H;         // LDS row of the chunk's first frame
-  int64_t cslot = T0 % capacity;  // ring slot of the chunk's first frame
+  // Lane (m, g) reads rows r + g * RPT + i of column m for a ring row r.
+  const float2* lane_hist = hist + g * RPT * K + m;
+  int crow = max_lag % H;          // LDS row of the chunk's first frame
+  int cslot = int(T0 % capacity);  // ring slot of the chunk's first frame
   prefetch(0, cslot);
-  for (int c = 0; c < len; c += S) {
+
+  // One chunk: copy its rows (prefetched one chunk earlier) into the LDS
+  // ring, start loading the next chunk, then sum the wave's lags. Every
+  // wave runs every chunk once, in order, so the barriers pair up.
+  auto chunk = [&](int c, auto&& body) {
     commit(crow);
     __syncthreads();
     cslot += S;
-    if (cslot >= capacity) cslot -= capacity;
+    if (cslot >= cap) cslot -= cap;
     if (c + S < len) prefetch(c + S, cslot);
-
-    const int rb = crow + g * RPT;  // reads stay inside the ring and its mirror
-    const int ub = c + g * RPT;     // window offset of this lane's first target
-    const bool full = c + S <= len;
-    float2 cur[RPT];
-#pragma unroll
-    for (int i = 0; i < RPT; ++i) cur[i] = hist[(rb + i) * K + m];
-    auto older = [&](int ts) {
-      int r = rb - ts;
+    // Rows of lag ts: the chunk's first row moved back by ts and wrapped
+    // once, all in scalar registers (crow and ts are wave-uniform); a
+    // lane's run then stays inside the ring and its mirror.
+    auto rows = [&](int ts) -> const float2* {
+      int r = crow - ts;
       if (r < 0) r += H;
-      return hist + r * K + m;
+      return lane_hist + r * K;
     };
-
-    // Older rows of a lag slot; slots past l_count have tau = 0 and read the
-    // current rows, so every read is in bounds and unconditional.
-    auto load_old = [&](float2 (&o)[RPT], int ts) {
-      const float2* src = older(ts);
+    float2 cur[RPT];
+    {
+      const float2* src = lane_hist + crow * K;
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) o[i] = src[i * K];
-    };
-    if (consecutive && full && c >= first_max) {
-      // Every target of the chunk has a partner for every lag of the run:
-      // rows rb - tau[0] - (MAXLW-1) .. rb - tau[0] + RPT - 1 serve them
-      // all, lag tau[0] + s reads win[MAXLW - 1 - s + i].
-      float2 win[WIN];
-      const float2* src = older(tau[0] + MAXLW - 1);
-#pragma unroll
-      for (int i = 0; i < WIN; ++i) win[i] = src[i * K];
-      dev::static_for<MAXLW>([&](auto SS) {
-        constexpr int s = decltype(SS)::value;
-        if (s < l_count) acc_plain(cur, win + (MAXLW - 1 - s), s);
-      });
-    } else {
-      // Per lag slot (wave-uniform): every target of the chunk has a
-      // partner (plain sums), some do (masked sums) or none (skipped). The
-      // older rows of slot s+1 are read while slot s is summed.
-      auto sum_slot = [&](const float2* o, int s) {
-        if (s < l_count) {
-          if (full && c >= first[s])
-            acc_plain(cur, o, s);
-          else if (c + S > first[s])
-            acc_masked(cur, o, s, ub);
-        }
-      };
-      float2 o0[RPT], o1[RPT];
-      load_old(o0, tau[0]);
-      dev::static_for<MAXLW>([&](auto SS) {
-        constexpr int s = decltype(SS)::value;
-        constexpr int nx = s + 1 < MAXLW ? s + 1 : s;
-        if constexpr ((s & 1) == 0) {
-          if constexpr (s + 1 < MAXLW) load_old(o1, tau[nx]);
-          sum_slot(o0, s);
-        } else {
-          if constexpr (s + 1 < MAXLW) load_old(o0, tau[nx]);
-          sum_slot(o1, s);
-        }
-      });
+      for (int i = 0; i < RPT; ++i) cur[i] = src[i * K];
     }
+    body(c, cur, rows);
     crow += S;
     if (crow >= H) crow -= H;
+  };
+
+  auto load_rows = [&](float2 (&o)[RPT], const float2* src) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) o[i] = src[i * K];
+  };
+  // Chunks where some target lacks a partner, or past the window end. Per
+  // lag slot (wave-uniform): every target of the chunk has a partner (plain
+  // sums), some do (masked sums) or none (skipped).
+  auto generic = [&](int c, const float2* cur, auto&& rows) {
+    const int ub = c + g * RPT;  // window offset of this lane's first target
+    const bool full = c + S <= len;
+    auto sum_slot = [&](const float2* o, int s) {
+      if (s < l_count) {
+        if (full && c >= first[s])
+          acc_plain(cur, o, s);
+        else if (c + S > first[s])
+          acc_masked(cur, o, s, ub);
+      }
+    };
+    float2 o0[RPT], o1[RPT];
+    load_rows(o0, rows(tau[0]));
+    dev::static_for<MAXLW>([&](auto SS) {
+      constexpr int s = decltype(SS)::value;
+      constexpr int nx = s + 1 < MAXLW ? s + 1 : s;
+      if constexpr ((s & 1) == 0) {
+        if constexpr (s + 1 < MAXLW) load_rows(o1, rows(tau[nx]));
+        sum_slot(o0, s);
+      } else {
+        if constexpr (s + 1 < MAXLW) load_rows(o0, rows(tau[nx]));
+        sum_slot(o1, s);
+      }
+    });
+  };
+  // A full chunk in which every target has a partner for each of the
+  // wave's L lags: no masks and no per-lag branches.
+  auto full_chunk = [&](auto NL, auto CONSEC, const float2* cur, auto&& rows) {
+    constexpr int L = decltype(NL)::value;
+    constexpr bool CONS = decltype(CONSEC)::value;
+    {
+      if constexpr (CONS) {
+        // Rows of lags tau[0] .. tau[0] + L - 1 overlap: one register
+        // window serves them all, lag tau[0] + s reads win[L - 1 - s + i].
+        constexpr int WL = RPT + L - 1;
+        float2 win[WL];
+        const float2* src = rows(tau[L - 1]);
+#pragma unroll
+        for (int i = 0; i < WL; ++i) win[i] = src[i * K];
+        dev::static_for<L>([&](auto SS) {
+          constexpr int s = decltype(SS)::value;
+          acc_plain(cur, win + (L - 1 - s), s);
+        });
+      } else {
+        // The older rows of lag s+1 are read while lag s is summed.
+        float2 o0[RPT], o1[RPT];
+        load_rows(o0, rows(tau[0]));
+        dev::static_for<L>([&](auto SS) {
+          constexpr int s = decltype(SS)::value;
+          if constexpr ((s & 1) == 0) {
+            if constexpr (s + 1 < L) load_rows(o1, rows(tau[s + 1]));
+            acc_plain(cur, o0, s);
+          } else {
+            if constexpr (s + 1 < L) load_rows(o0, rows(tau[s + 1]));
+            acc_plain(cur, o1, s);
+          }
+        });
+      }
+    }
+  };
+
+  // Chunks [0, ca): some target of the wave's lags may lack a partner;
+  // [ca, lenS): full chunks; [lenS, len): the partial last chunk. A wave
+  // has MAXLW or MAXLW - 1 lags (helper waves none); the full-chunk loop is
+  // specialised on that count and on consecutive lags, so the wave's
+  // accumulators stay in place through each loop.
+  const int lenS = (len / S) * S;
+  int ca = (first_max + S - 1) / S * S;
+  if (ca > lenS) ca = lenS;
+  int c = 0;
+  for (; c < ca; c += S) chunk(c, generic);
+  constexpr int LS = MAXLW > 1 ? MAXLW - 1 : 1;
+  using LMax = std::integral_constant<int, MAXLW>;
+  using LLess = std::integral_constant<int, LS>;
+  using Yes = std::true_type;
+  using No = std::false_type;
+  if (l_count == MAXLW && consecutive) {
+    for (; c < lenS; c += S)
+      chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LMax{}, Yes{}, cur, rows); });
+  } else if (l_count == MAXLW) {
+    for (; c < lenS; c += S)
+      chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LMax{}, No{}, cur, rows); });
+  } else if (MAXLW > 1 && l_count == LS && consecutive) {
+    for (; c < lenS; c += S)
+      chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LLess{}, Yes{}, cur, rows); });
+  } else if (MAXLW > 1 && l_count == LS) {
+    for (; c < lenS; c += S)
+      chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LLess{}, No{}, cur, rows); });
+  } else {
+    // Waves without lags only copy rows.
+    for (; c < lenS; c += S) chunk(c, [](int, const float2*, auto&&) {});
   }
+  for (; c < len; c += S) chunk(c, generic);
 
   // Lanes g = 0..G-1 of one mode hold partial sums over disjoint frames;
   // their total goes through LDS so the workgroup adds its K x n_lags block
@@ -267,46 +327,56 @@ __global__ __launch_bounds__(64 * kMaxPairWaves) void pair_kernel(
   }
 }
 
-template <int K, int P>
+template <int K, int P, int NW>
 hipError_t pair_launch(const float2* ring, const float2* refspec, const float2* fscale,
-                       int64_t n_modes, int64_t mode_stride,
-                       int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
-                       int n_lags, int max_lag, float* acc, int acc_pitch, int hist, int waves,
-                       size_t lds, hipStream_t s) {
+                       int64_t n_modes, int64_t mode_stride, int64_t capacity, int64_t T0,
+                       int64_t T1, const int32_t* lags, int n_lags, int max_lag, float* acc,
+                       int acc_pitch, int hist, int waves, size_t lds, hipStream_t s) {
   // Allow the LDS history beyond the default dynamic limit; a failure here
   // shows up as a launch error below.
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_kernel<K, P>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_kernel<K, P, NW>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
   const int64_t blocks = (n_modes + K - 1) / K;
-  const int launched = waves < 4 ? 4 : waves;  // extra waves only help load
-  hipLaunchKernelGGL((pair_kernel<K, P>), dim3(unsigned(blocks)), dim3(64 * launched), lds, s,
+  hipLaunchKernelGGL((pair_kernel<K, P, NW>), dim3(unsigned(blocks)), dim3(64 * NW), lds, s,
                      ring, refspec, fscale, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,
                      max_lag, acc, acc_pitch, hist, waves);
   return hipGetLastError();
 }
 
+// Up to 8 lag waves run in 8-wave workgroups; more (only with 6 or more
+// lags per wave) in 12-wave ones.
 template <int K>
 hipError_t pair_dispatch(int per_wave, const float2* ring, const float2* refspec,
-                         const float2* fscale, int64_t n_modes,
-                         int64_t mode_stride, int64_t capacity, int64_t T0, int64_t T1,
-                         const int32_t* lags, int n_lags, int max_lag, float* acc,
-                         int acc_pitch, int hist, int waves, size_t lds, hipStream_t s) {
-#define NFS_PAIR_P(PP)                                                                     \
-  case PP:                                                                                 \
-    return pair_launch<K, PP>(ring, refspec, fscale, n_modes, mode_stride, capacity, T0,  \
-                              T1, lags, n_lags, max_lag, acc, acc_pitch, hist, waves, lds, \
-                              s);
-  switch (per_wave) {
-    NFS_PAIR_P(1)
-    NFS_PAIR_P(2)
-    NFS_PAIR_P(3)
-    NFS_PAIR_P(4)
-    NFS_PAIR_P(5)
-    NFS_PAIR_P(6)
-    NFS_PAIR_P(7)
-    NFS_PAIR_P(8)
-    default: return hipErrorInvalidValue;
+                         const float2* fscale, int64_t n_modes, int64_t mode_stride,
+                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
+                         int n_lags, int max_lag, float* acc, int acc_pitch, int hist, int waves,
+                         size_t lds, hipStream_t s) {
+#define NFS_PAIR_P(PP, NWW)                                                                \
+  return pair_launch<K, PP, NWW>(ring, refspec, fscale, n_modes, mode_stride, capacity,   \
+                                 T0, T1, lags, n_lags, max_lag, acc, acc_pitch, hist,       \
+                                 waves, lds, s)
+  if (waves <= 8) {
+    switch (per_wave) {
+      case 1: NFS_PAIR_P(1, 8);
+      case 2: NFS_PAIR_P(2, 8);
+      case 3: NFS_PAIR_P(3, 8);
+      case 4: NFS_PAIR_P(4, 8);
+      case 5: NFS_PAIR_P(5, 8);
+      case 6: NFS_PAIR_P(6, 8);
+      case 7: NFS_PAIR_P(7, 8);
+      case 8: NFS_PAIR_P(8, 8);
+      default: return hipErrorInvalidValue;
+    }
   }
+  if (waves <= 12) {
+    switch (per_wave) {
+      case 6: NFS_PAIR_P(6, 12);
+      case 7: NFS_PAIR_P(7, 12);
+      case 8: NFS_PAIR_P(8, 12);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipErrorInvalidValue;
 #undef NFS_PAIR_P
 }
 

@@ -68,6 +68,7 @@ def test_descriptor_validation():
     assert code(capacity=4) == "NFS_E_CAPACITY"
     assert code(lags=[0], capacity=1) == "NFS_OK"
     assert code(capacity=-1) == "NFS_E_CAPACITY"
+    assert code(capacity=2**31) == "NFS_E_CAPACITY"
 
 
 def test_unsupported_options_are_rejected():
