@@ -82,12 +82,18 @@ static bool plan_group(const std::vector<int32_t>& lags, int first, int count,
   g->count = count;
   g->max_lag = lags[first + count - 1];
   g->modes = 0;
-  for (int K : {64, 32, 16, 8}) {
-    const int S = pair_chunk(K);
-    const int H = int(align_up(size_t(g->max_lag + 2 * S), S));
-    const size_t lds = size_t(H + pair_mirror(K)) * K * 8;
-    if (lds <= size_t(kLdsBytes)) {
-      g->modes = K;
+  // Two workgroups per CU hide each other's barrier and LDS waits: the first
+  // choice is 16 modes per workgroup with LDS for two workgroups, then 16 or
+  // 8 modes with LDS for one (the 8-wave kernels with 16 or 8 modes fit the
+  // registers of two workgroups per CU).
+  const int S = kPairChunk;
+  const int H = int(align_up(size_t(g->max_lag + 2 * S), S));
+  const struct { int K; size_t budget; } choices[] = {
+      {16, size_t(kLdsBytes) / 2}, {16, size_t(kLdsBytes)}, {8, size_t(kLdsBytes)}};
+  for (const auto& ch : choices) {
+    const size_t lds = size_t(H + kPairMirror) * ch.K * 8;
+    if (lds <= ch.budget) {
+      g->modes = ch.K;
       g->hist = H;
       g->lds = lds;
       break;

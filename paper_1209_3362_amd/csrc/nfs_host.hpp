@@ -15,16 +15,16 @@ namespace nfs {
 constexpr int kMinN = 16;
 constexpr int kMaxN = 4096;
 constexpr size_t kAlign = 256;
-// Frames of the time series handled per step of the pair kernel with K
-// modes per workgroup (every lane then holds at most 16 target frames).
-constexpr int pair_chunk(int K) { return K == 64 ? 16 : 32; }
+// Frames of the time series handled per step of the pair kernel (with K
+// modes per workgroup every lane holds 32 * K / 64 target frames).
+constexpr int kPairChunk = 32;
 // Most lags one wave of the pair kernel accumulates at once, and most waves
 // per workgroup; a launch handles at most their product.
 constexpr int kMaxLagsPerWave = 8;
 constexpr int kMaxPairWaves = 12;
 // LDS rows mirrored after the pair kernel's history ring: from a row of the
 // ring a lane reads up to S + kMaxLagsPerWave - 2 rows further on.
-constexpr int pair_mirror(int K) { return pair_chunk(K) + kMaxLagsPerWave; }
+constexpr int kPairMirror = kPairChunk + kMaxLagsPerWave;
 // LDS a workgroup may allocate on gfx950.
 constexpr int kLdsBytes = 160 * 1024;
 // Largest delay the pair kernel's on-chip history supports (K = 8 modes).

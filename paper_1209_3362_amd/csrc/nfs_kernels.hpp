@@ -39,7 +39,7 @@ hipError_t launch_col_pass(int n, bool reference, const float2* inter, const dou
 // over t in [T0, T1) with t - lag >= 0 (acc is mode-major), where
 // I_t = ring slot of t + fscale[slot].y * refspec (refspec has mode_stride
 // entries, 0 at k = 0). Frames [max(0, T0 - max lag), T1) must be in the
-// ring. `modes` per workgroup (64, 32, 16 or 8), `hist` LDS rows; wave w
+// ring. `modes` per workgroup (16 or 8), `hist` LDS rows; wave w
 // sums lags [w * per_wave, (w + 1) * per_wave) (per_wave <= kMaxLagsPerWave).
 hipError_t launch_pairs(const float2* ring, const float2* refspec, const float2* fscale,
                         int64_t n_modes, int64_t mode_stride,

@@ -12,7 +12,10 @@
 // loop is one LDS read (the older frame), two subtractions and two FMAs; a
 // wave whose lags are consecutive integers reads one register window of
 // older frames shared by all its lags instead. The first rows of the LDS
-// ring are mirrored after its end so a lane's run of rows never wraps.
+// ring are mirrored after its end so a lane's run of rows never wraps. With
+// 16 modes per workgroup the history of lags up to about 500 frames fits
+// half the LDS, so two workgroups share a CU and each covers the other's
+// barrier and LDS waits.
 //
 // A ring slot holds sigma_t F[frame_t - reference]; the spectrum the pairs
 // use is that plus (sigma_t - sigma_ref) F[reference], i.e. the normalised
@@ -36,11 +39,12 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
     const float2* __restrict__ fscale, int64_t n_modes, int64_t mode_stride, int64_t capacity,
     int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags, int max_lag,
     float* __restrict__ acc, int acc_pitch, int H, int lag_waves) {
-  constexpr int S = pair_chunk(K);  // frames per chunk
+  static_assert(K == 16 || K == 8, "16 or 8 modes per workgroup");
+  constexpr int S = kPairChunk;  // frames per chunk
   constexpr int G = 64 / K;         // lanes sharing one mode inside a wave
   constexpr int RPT = S / G;        // target rows per lane per chunk
   constexpr int V4 = K / 2;         // float4 (two modes) per ring row of the tile
-  constexpr int MR = pair_mirror(K);    // rows mirrored past the end of the LDS ring
+  constexpr int MR = kPairMirror;  // rows mirrored past the end of the LDS ring
   // A wrapped row r < H plus a lane's run (at most S + MAXLW - 2 rows on)
   // must stay below H + MR.
   static_assert(MR >= S + MAXLW - 2, "mirror too short for a lane's row run");
@@ -393,8 +397,6 @@ hipError_t launch_pairs(const float2* ring, const float2* refspec, const float2*
                              capacity, T0, T1, lags, n_lags, max_lag, acc, acc_pitch, hist, \
                              waves, lds, s);
   switch (modes) {
-    NFS_PAIR_CASE(64)
-    NFS_PAIR_CASE(32)
     NFS_PAIR_CASE(16)
     NFS_PAIR_CASE(8)
     default: return hipErrorInvalidValue;
