@@ -273,61 +273,60 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN>())) v
 }
 
 // ---------------------------------------------------------------------------
-// Frame scales from the row sums, in a fixed order (strided partial sums,
-// butterfly per wave, waves in index order). REF: the rows were the
-// reference image; refscal = {S_ref, n^2/S_ref}. Otherwise the rows were
-// (image - reference) of frame t0 + f: S = S_ref + sum, sigma = n^2/S and
-// fscale[(t0 + f) mod capacity] = {sigma, sigma - sigma_ref}; a frame whose
-// S is not positive and finite gets sigma = 0 and sets bit 0 of *status.
-template <bool REF>
-__global__ __launch_bounds__(256) void frame_scale_kernel(int n, const double* __restrict__ rowsum,
-                                                          double* __restrict__ refscal,
-                                                          float2* __restrict__ fscale,
-                                                          int64_t t0, int64_t capacity,
-                                                          int32_t* __restrict__ status) {
+// Scale of the reference image from its row sums, in a fixed order
+// (strided partial sums, butterfly per wave, waves in index order):
+// refscal = {S_ref, n^2/S_ref}, sigma 0 (and bit 0 of *status) when S_ref
+// is not positive and finite. Frames' scales are formed in the column pass.
+__global__ __launch_bounds__(256) void ref_scale_kernel(int n, const double* __restrict__ rowsum,
+                                                        double* __restrict__ refscal,
+                                                        int32_t* __restrict__ status) {
   __shared__ double red[4];
-  const int f = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   double s = 0.0;
-  for (int y = tid; y < n; y += 256) s += rowsum[int64_t(f) * n + y];
+  for (int y = tid; y < n; y += 256) s += rowsum[y];
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
   if ((tid & 63) == 0) red[tid >> 6] = s;
   __syncthreads();
   if (tid == 0) {
-    const double part = ((red[0] + red[1]) + red[2]) + red[3];
-    const double total = REF ? part : refscal[0] + part;
+    const double total = ((red[0] + red[1]) + red[2]) + red[3];
     const bool bad = !(total > 0.0) || !isfinite(total);
-    const double sigma = bad ? 0.0 : double(n) * double(n) / total;
-    if constexpr (REF) {
-      refscal[0] = total;
-      refscal[1] = sigma;
-    } else {
-      fscale[(t0 + f) % capacity] = make_float2(float(sigma), float(sigma - refscal[1]));
-      if (bad) atomicOr(status, 1);
-    }
+    refscal[0] = total;
+    refscal[1] = bad ? 0.0 : double(n) * double(n) / total;
+    if (bad) atomicOr(status, 1);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Column pass over CW columns: DFT_N over the rows of each frame of the
 // group. REF: store the reference transform F[reference] unscaled in
-// refspec. Otherwise store sigma * X (X = F[frame - reference]) into ring
-// slot (t0 + f) mod capacity, sigma from that slot's fscale entry. Both
-// store 0 at k = 0 and only the stored modes (k_x < row_width[r]); the
-// pair kernel adds (sigma - sigma_ref) * refspec when it reads a slot.
-// Per-thread store offsets are computed once; the next frame's columns are
-// loaded during the second level.
+// refspec. Otherwise the rows were (frame - reference) of frame t0 + f:
+// every workgroup of the frame forms S = S_ref + (sum of its row sums) in
+// the same fixed order (strided partial sums, butterfly per wave, waves in
+// index order) and sigma = n^2 / S, stores sigma * X (X = F[frame -
+// reference]) into ring slot (t0 + f) mod capacity, and the frame's first
+// column group writes fscale[slot] = {sigma, sigma - sigma_ref}; a frame
+// whose S is not positive and finite gets sigma = 0 and sets bit 0 of
+// *status. Both store 0 at k = 0 and only the stored modes (k_x <
+// row_width[r]); the pair kernel adds (sigma - sigma_ref) * refspec when it
+// reads a slot. Per-thread store offsets are computed once; the next
+// frame's columns are loaded during the second level.
 template <int N, bool REF>
 __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_kernel(
-    const float2* __restrict__ inter, const float2* __restrict__ fscale, int nframes,
-    int per_group, int64_t t0, int64_t capacity, int64_t mode_stride, int64_t n_modes,
-    const int32_t* __restrict__ row_width, const int32_t* __restrict__ row_offset,
-    const float2* __restrict__ tw, float2* __restrict__ ring, float2* __restrict__ refspec) {
+    const float2* __restrict__ inter, const double* __restrict__ rowsum,
+    const double* __restrict__ refscal, float2* __restrict__ fscale, int32_t* __restrict__ status,
+    int nframes, int per_group, int64_t t0, int64_t capacity, int64_t mode_stride,
+    int64_t n_modes, const int32_t* __restrict__ row_width,
+    const int32_t* __restrict__ row_offset, const float2* __restrict__ tw,
+    float2* __restrict__ ring, float2* __restrict__ refspec) {
   using C = ColCfg<N>;
   constexpr int P1 = C::P1, P2 = C::P2, Q = C::Q, CP = C::CP, CW = C::CW;
   constexpr int THREADS = C::THREADS, GROUPS = C::GROUPS, TILES = C::TILES;
+  constexpr int WW = THREADS < 64 ? THREADS : 64;  // lanes of a (possibly partial) wave
+  constexpr int NWAVES = (THREADS + 63) / 64;
   __shared__ float2 lds[CW * CP];
   __shared__ float2 twl[tw_len(N)];
+  __shared__ double red[NWAVES];
 
   // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
   // neighbouring column groups of a frame (which write the two halves of
@@ -374,9 +373,19 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
   float2* col_lds = lds + c * CP;
   int64_t slot = (t0 + f_begin) % capacity;
   const uint32_t spec_bytes = uint32_t(n_modes) * 8u;
+  double s_ref = 0.0, sigma_ref = 0.0;
+  if constexpr (!REF) {
+    s_ref = refscal[0];
+    sigma_ref = refscal[1];
+  }
   __syncthreads();
 
   for (int f = f_begin; f < f_end; ++f) {
+    // This thread's share of the frame's pixel sum (loads issued early).
+    double part = 0.0;
+    if constexpr (!REF) {
+      for (int y = tid; y < N; y += THREADS) part += rowsum[int64_t(f) * N + y];
+    }
     if constexpr (!CACHE) load_cols(v, f);
     dft<P2>(v);
     static_for<P2>([&](auto K2) {
@@ -385,13 +394,30 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
       if constexpr (k2 != 0) yv = cmul(yv, twl[tw_skew((j1 * k2) & (N - 1))]);
       col_lds[k2 * (P1 + 1) + j1] = yv;
     });
+    if constexpr (!REF) {
+#pragma unroll
+      for (int o = WW / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, WW);
+      if ((tid & 63) == 0) red[tid >> 6] = part;
+    }
     __syncthreads();
     if constexpr (CACHE) {
       if (f + 1 < f_end) load_cols(v, f + 1);
     }
 
     float scale = 1.f;
-    if constexpr (!REF) scale = fscale[slot].x;
+    if constexpr (!REF) {
+      double tot = red[0];
+#pragma unroll
+      for (int w = 1; w < NWAVES; ++w) tot += red[w];
+      const double S = s_ref + tot;
+      const bool bad = !(S > 0.0) || !isfinite(S);
+      const double sigma = bad ? 0.0 : double(N) * double(N) / S;
+      scale = float(sigma);
+      if (grp == 0 && tid == 0) {
+        fscale[slot] = make_float2(float(sigma), float(sigma - sigma_ref));
+        if (bad) atomicOr(status, 1);
+      }
+    }
     const BufferRsrc dst = make_buffer(REF ? refspec : ring + slot * mode_stride, spec_bytes);
     static_for<Q>([&](auto QQ) {
       constexpr int q = decltype(QQ)::value;
@@ -457,17 +483,14 @@ hipError_t col_launch(bool reference, const float2* inter, const double* rowsum,
   const int per = frames_per_group(nframes, C::GROUPS);
   const int64_t blocks = int64_t(C::GROUPS) * ((nframes + per - 1) / per);
   if (reference) {
-    hipLaunchKernelGGL(frame_scale_kernel<true>, dim3(unsigned(nframes)), dim3(256), 0, s, N,
-                       rowsum, refscal, fscale, t0, capacity, status);
+    hipLaunchKernelGGL(ref_scale_kernel, dim3(1), dim3(256), 0, s, N, rowsum, refscal, status);
     hipLaunchKernelGGL((col_pass_kernel<N, true>), dim3(unsigned(blocks)), dim3(C::THREADS), 0,
-                       s, inter, fscale, nframes, per, t0, capacity, mode_stride, n_modes,
-                       row_width, row_offset, tw, ring, refspec);
+                       s, inter, rowsum, refscal, fscale, status, nframes, per, t0, capacity,
+                       mode_stride, n_modes, row_width, row_offset, tw, ring, refspec);
   } else {
-    hipLaunchKernelGGL(frame_scale_kernel<false>, dim3(unsigned(nframes)), dim3(256), 0, s, N,
-                       rowsum, refscal, fscale, t0, capacity, status);
     hipLaunchKernelGGL((col_pass_kernel<N, false>), dim3(unsigned(blocks)), dim3(C::THREADS), 0,
-                       s, inter, fscale, nframes, per, t0, capacity, mode_stride, n_modes,
-                       row_width, row_offset, tw, ring, refspec);
+                       s, inter, rowsum, refscal, fscale, status, nframes, per, t0, capacity,
+                       mode_stride, n_modes, row_width, row_offset, tw, ring, refspec);
   }
   return hipGetLastError();
 }

@@ -18,10 +18,11 @@ hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* 
                            const float* window, int nframes, float2* inter, double* rowsum,
                            const float2* tw, hipStream_t s);
 
-// Frame scales from the row sums, then the column pass (per column k_x:
-// complex transform over the n rows).
-// reference == true: the rows are the reference image (one frame); store its
-// transform unscaled in refspec (0 at k = 0) and refscal = {S_ref, n^2/S_ref}.
+// Column pass (per column k_x: complex transform over the n rows), with the
+// frame scales formed from the row sums.
+// reference == true: the rows are the reference image (one frame); set
+// refscal = {S_ref, n^2/S_ref} and store its transform unscaled in refspec
+// (0 at k = 0).
 // reference == false: the rows are (frame - reference); with
 // sigma = n^2 / (S_ref + row sums), fscale[slot] = {sigma, sigma - sigma_ref}
 // and sigma * X, 0 at k = 0, stored for frame f in ring slot

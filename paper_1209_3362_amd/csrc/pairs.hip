@@ -96,16 +96,29 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
                        fmaf(d, R.w, v.w));
   };
 
-  // History from earlier windows: frames [max(0, T0 - max_lag), T0).
+  // History from earlier windows: frames [max(0, T0 - max_lag), T0), all
+  // threads copying float4 elements in parallel (unrolled by 4 so several
+  // loads are in flight). Frame T0 - pre + r goes to LDS row
+  // (max_lag - pre + r) mod H.
   {
     const int pre = int(T0 - max_lag > 0 ? max_lag : T0);
-    int64_t slot = (T0 - pre) % capacity;
-    for (int r = 0; r < pre; ++r) {
+    const int slot0 = int((T0 - pre) % capacity);
+    const int total = pre * V4;
+    const int cap0 = int(capacity);
+    auto copy_one = [&](int e) {
+      const int r = e / V4, col2 = e % V4;
+      int slot = slot0 + r;
+      if (slot >= cap0) slot -= cap0;
+      const float4 v = slot_row(slot)[col2];
       const float d = fscale[slot].y;
-      for (int col2 = threadIdx.x; col2 < V4; col2 += nthreads)
-        put_row((max_lag - pre + r) % H, col2, corrected(slot_row(slot)[col2], d, ref4[col2]));
-      if (++slot == capacity) slot = 0;
+      put_row((max_lag - pre + r) % H, col2, corrected(v, d, ref4[col2]));
+    };
+    int e = threadIdx.x;
+    for (; e + 3 * nthreads < total; e += 4 * nthreads) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) copy_one(e + u * nthreads);
     }
+    for (; e < total; e += nthreads) copy_one(e);
   }
 
   // Thread e < S * V4 copies float4 column e % V4 of chunk row e / V4 (whole
