@@ -135,6 +135,18 @@ nfs_status nfs_accumulate(nfs_handle h);
 nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
                                   int64_t* lag_pairs, int32_t* status);
 
+/* 2D power spectra, the per-delay "differences area" of the processing
+ * section (Fig. 2): finish the pair sums for every frame pushed so far and
+ * write, on the device, S float [n_lags][n][n/2 + 1]: entry [l][r][k_x] is
+ *   P_tau(k) = (1 / (N - tau)) * sum_t |I_t(k) - I_{t+tau}(k)|^2
+ * for tau = lags[l] and the mode (k_y, k_x), r the transform-order row of
+ * k_y, at the stored modes (k_x < n/2, |k| < n/2); 0 at the other modes
+ * (the k_x = n/2 column and the corners, which belong to no bin); NaN for
+ * every mode of a delay with no pair (N - tau <= 0). The sums are FP32 per
+ * mode, the division is done in double and rounded once. S is owned by the
+ * caller. Enqueued on the plan's stream. */
+nfs_status nfs_power_spectra_2d(nfs_handle h, float* S);
+
 /* Forget all frames and sums (enqueued); the plan can be reused. */
 nfs_status nfs_reset(nfs_handle h);
 

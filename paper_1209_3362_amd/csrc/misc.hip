@@ -48,6 +48,34 @@ __global__ void expand_kernel(int n, const float2* __restrict__ spec,
   }
 }
 
+// P_tau(k) = S_tau(k) / (N - tau) from the mode-major sums acc[mode][lag]
+// onto [n_lags][n][n/2 + 1]; 0 where no mode is stored, NaN for a delay
+// without pairs.
+__global__ void power_kernel(int n, int n_lags, const float* __restrict__ acc,
+                             const int32_t* __restrict__ row_width,
+                             const int32_t* __restrict__ row_offset,
+                             const int32_t* __restrict__ lags, int64_t n_frames,
+                             float* __restrict__ out) {
+  const int h = n / 2, w = h + 1;
+  const int64_t plane = int64_t(n) * w;
+  const int64_t total = int64_t(n_lags) * plane;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += int64_t(gridDim.x) * blockDim.x) {
+    const int l = int(i / plane);
+    const int64_t rem = i - int64_t(l) * plane;
+    const int r = int(rem / w), kx = int(rem % w);
+    const int64_t pairs = n_frames - lags[l];
+    float v = 0.f;
+    if (pairs <= 0) {
+      v = __builtin_nanf("");
+    } else if (kx < h && kx < row_width[r]) {
+      const int64_t m = row_offset[r] + kx;
+      v = float(double(acc[m * n_lags + l]) / double(pairs));
+    }
+    out[i] = v;
+  }
+}
+
 unsigned grid_for(int64_t items, int threads) {
   int64_t g = (items + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -77,6 +105,15 @@ hipError_t launch_expand_spectrum(int n, const float2* ring, int64_t slot, int64
   hipLaunchKernelGGL(expand_kernel, dim3(grid_for(int64_t(n) * (n / 2), 256)), dim3(256), 0, s,
                      n, ring + slot * mode_stride, row_width, row_offset, refspec, fscale + slot,
                      out);
+  return hipGetLastError();
+}
+
+hipError_t launch_power_spectra(int n, int n_lags, const float* acc, const int32_t* row_width,
+                                const int32_t* row_offset, const int32_t* lags,
+                                int64_t n_frames, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(power_kernel,
+                     dim3(grid_for(int64_t(n_lags) * n * (n / 2 + 1), 256)), dim3(256), 0, s, n,
+                     n_lags, acc, row_width, row_offset, lags, n_frames, out);
   return hipGetLastError();
 }
 

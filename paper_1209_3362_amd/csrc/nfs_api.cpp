@@ -281,6 +281,18 @@ nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
   return NFS_OK;
 }
 
+nfs_status nfs_power_spectra_2d(nfs_handle h, float* S) {
+  if (!is_live(h)) return NFS_E_STATE;
+  if (!S) return fail(h, NFS_E_ARG, "S is NULL");
+  nfs_status st = flush_pairs(h);
+  if (st != NFS_OK) return st;
+  const nfs::Layout& L = h->L;
+  hipError_t e = nfs::launch_power_spectra(L.n, L.n_lags, h->acc, h->width, h->offset, h->lags,
+                                           h->t_pushed, S, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "power spectra launch");
+  return NFS_OK;
+}
+
 nfs_status nfs_reset(nfs_handle h) {
   if (!is_live(h)) return NFS_E_STATE;
   return clear_sums(h);

@@ -74,4 +74,11 @@ hipError_t launch_expand_spectrum(int n, const float2* ring, int64_t slot,
                                   const int32_t* row_offset, const float2* refspec,
                                   const float2* fscale, float2* out, hipStream_t s);
 
+// P_tau(k) = acc[mode][l] / (n_frames - lags[l]) written to out
+// [n_lags][n][n/2 + 1] (0 at modes that are not stored, NaN for every mode
+// of a delay with n_frames - lag <= 0).
+hipError_t launch_power_spectra(int n, int n_lags, const float* acc, const int32_t* row_width,
+                                const int32_t* row_offset, const int32_t* lags,
+                                int64_t n_frames, float* out, hipStream_t s);
+
 }  // namespace nfs

@@ -76,6 +76,7 @@ def load_library():
         "nfs_mode_count": (i32, [P, ctypes.POINTER(i64)]),
         "nfs_bin_map": (i32, [P, P]),
         "nfs_copy_spectrum": (i32, [P, i64, P]),
+        "nfs_power_spectra_2d": (i32, [P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -193,6 +194,15 @@ class Plan:
         if sync:
             self.stream.synchronize()
         return D, counts, pairs, status
+
+    def power_spectra(self, sync=True):
+        """P_tau(k) as float32 [n_lags][n][n/2 + 1] (nfs_power_spectra_2d)."""
+        out = torch.empty((len(self.lags), self.n, self.n // 2 + 1), dtype=torch.float32,
+                          device=self.device)
+        self._check(self.lib.nfs_power_spectra_2d(self.handle, _ptr(out)))
+        if sync:
+            self.stream.synchronize()
+        return out
 
     def bin_map(self):
         out = torch.empty((self.n, self.n // 2), dtype=torch.int32, device=self.device)
