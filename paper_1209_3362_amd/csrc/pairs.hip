@@ -138,12 +138,13 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
   // masked targets ever meet it); every other row is a frame of the window
   // (len <= capacity), so c + dt < len <= cap and one wrap of cslot + dt
   // lands in [0, cap).
+  const uint32_t ucap = uint32_t(cap), ulen = uint32_t(len), updt = uint32_t(pdt);
   auto prefetch = [&](int c, int cslot) {
     if (loader) {
-      const int dt = c + pdt < len ? pdt : 0;
-      int slot = cslot + dt;
-      if (slot >= cap) slot -= cap;
-      pf = pbase[uint64_t(uint32_t(slot)) * stride4];
+      const uint32_t dt = uint32_t(c) + updt < ulen ? updt : 0u;
+      uint32_t slot = uint32_t(cslot) + dt;
+      slot = slot >= ucap ? slot - ucap : slot;
+      pf = pbase[size_t(slot) * stride4];
       pd = fscale[slot].y;
     }
   };
@@ -232,10 +233,19 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
     const bool full = c + S <= len;
     auto sum_slot = [&](const float2* o, int s) {
       if (s < l_count) {
-        if (full && c >= first[s])
+        if (full && c >= first[s]) {
           acc_plain(cur, o, s);
-        else if (c + S > first[s])
-          acc_masked(cur, o, s, ub);
+        } else if (c + S > first[s]) {
+          // Targets [lo, hi) of the chunk have partners. When both ends fall
+          // on lane boundaries every lane's run is wholly in or out: plain
+          // sums on the lanes that are in; otherwise per-target selects.
+          const int lo = max(first[s] - c, 0), hi = min(len - c, S);
+          if (lo % RPT == 0 && hi % RPT == 0) {
+            if (g * RPT >= lo && g * RPT < hi) acc_plain(cur, o, s);
+          } else {
+            acc_masked(cur, o, s, ub);
+          }
+        }
       }
     };
     float2 o0[RPT], o1[RPT];
