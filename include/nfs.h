@@ -67,18 +67,33 @@ typedef enum {
 
 /* Pixel type of the frames passed to nfs_push_frames. */
 enum { NFS_IN_U16 = 0, NFS_IN_F32 = 1 };
-/* Storage type of the resident spectra (only FP32 is implemented). */
-enum { NFS_SPEC_F32 = 0 };
-/* Per-mode pair accumulation (only plain FP32 is implemented). */
-enum { NFS_ACC_PLAIN = 0 };
+/* Storage type of the resident spectra. Each stored value is
+ * sigma_t F[u_t - u_ref] (the frame's transform minus the scaled transform of
+ * the first frame of the sequence, fluctuation-sized); the pair kernel adds
+ * (sigma_t - sigma_ref) F[u_ref] back in FP32, so differences are those of
+ * the normalised transforms.
+ *   NFS_SPEC_F32:  FP32 real and imaginary parts, 8 bytes per mode;
+ *   NFS_SPEC_BF16: each part rounded to BF16 (nearest, ties to even),
+ *                  4 bytes per mode;
+ *   NFS_SPEC_F16:  each part multiplied by 2^e_t and rounded to FP16, with
+ *                  e_t the largest integer for which
+ *                  2^e_t * sigma_t * sum_x |u_t(x) - u_ref(x)| <= 65504 (no
+ *                  overflow), 4 bytes per mode.
+ * Differences, squares and sums are FP32 in every case (precision form). */
+enum { NFS_SPEC_F32 = 0, NFS_SPEC_BF16 = 1, NFS_SPEC_F16 = 2 };
+/* Per-mode pair accumulation.
+ *   NFS_ACC_PLAIN: FP32 running sums;
+ *   NFS_ACC_KAHAN: FP32 sums over each chunk of 32 target frames, added to
+ *                  the running sum with Kahan compensation. */
+enum { NFS_ACC_PLAIN = 0, NFS_ACC_KAHAN = 1 };
 
 typedef struct {
   int32_t n;            /* frame side; frames are n x n, row-major; power of
                            two in [16, 4096] (the paper processed 32x32 up to
                            4k x 4k images, processing section)                */
   int32_t in_dtype;     /* NFS_IN_U16 or NFS_IN_F32                           */
-  int32_t spec_dtype;   /* NFS_SPEC_F32                                       */
-  int32_t accum;        /* NFS_ACC_PLAIN                                      */
+  int32_t spec_dtype;   /* NFS_SPEC_F32, NFS_SPEC_BF16 or NFS_SPEC_F16        */
+  int32_t accum;        /* NFS_ACC_PLAIN or NFS_ACC_KAHAN                     */
   int32_t n_lags;       /* number of delays, >= 1                             */
   const int32_t* lags;  /* host array of n_lags delays in frames, strictly
                            increasing, lags[0] >= 0; copied by nfs_plan. The

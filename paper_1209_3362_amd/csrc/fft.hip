@@ -94,7 +94,7 @@ inline int frames_per_group(int nframes, int groups_per_frame) {
 // Two row-pass workgroups per CU where a thread's state fits the register
 // budget of two waves per SIMD without spilling (integer pixels, no window,
 // up to 1024 pixels per row).
-template <int N, typename T, bool WIN>
+template <int N, typename T, bool WIN, bool ABS>
 constexpr int row_min_waves() {
   return N <= 512 || (N == 1024 && std::is_same<T, uint16_t>::value && !WIN) ? 2 : 1;
 }
@@ -123,12 +123,13 @@ __device__ __forceinline__ typename RawPair<T>::type load_pair(const T* p) {
 // threads sit in one wave and only they touch the row's LDS, so the frame
 // loop has no workgroup barrier. A workgroup owns R rows and loops over up
 // to `per_group` frames of the batch, loading the next frame's pixels while
-// it transforms the current one.
-template <int N, typename T, bool WIN>
-__global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN>())) void row_pass_kernel(
+// it transforms the current one. ABS: also write rowabs[f][y], the row's sum
+// of |what is transformed| (bounds every coefficient of the frame).
+template <int N, typename T, bool WIN, bool ABS>
+__global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN, ABS>())) void row_pass_kernel(
     const T* __restrict__ frames, const T* __restrict__ ref, const float* __restrict__ window,
     int nframes, int per_group, float2* __restrict__ inter, double* __restrict__ rowsum,
-    const float2* __restrict__ tw) {
+    double* __restrict__ rowabs, const float2* __restrict__ tw) {
   using C = RowCfg<N>;
   using Raw = typename RawPair<T>::type;
   constexpr bool U16 = std::is_same<T, uint16_t>::value;
@@ -174,8 +175,8 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN>())) v
 
   for (int f = f_begin; f < f_end; ++f) {
     float2 v[P2];
-    int si = 0;
-    double sd = 0.0;
+    int si = 0, sia = 0;
+    double sd = 0.0, sda = 0.0;
 #pragma unroll
     for (int j2 = 0; j2 < P2; ++j2) {
       float a, b;
@@ -194,6 +195,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN>())) v
         a = float(da);
         b = float(db);
         if constexpr (!WIN) si += da + db;
+        if constexpr (ABS && !WIN) sia += abs(da) + abs(db);
       } else {
         a = px.x - rp.x;
         b = px.y - rp.y;
@@ -205,6 +207,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN>())) v
         b *= ww.y;
       }
       if constexpr (!U16 || WIN) sd += double(a) + double(b);
+      if constexpr (ABS && (!U16 || WIN)) sda += double(fabsf(a)) + double(fabsf(b));
       v[j2] = make_float2(a, b);
     }
     // Next frame's pixels are in flight while this one is transformed.
@@ -223,6 +226,19 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN>())) v
       s = sd;
     }
     if (j1 == 0) rowsum[int64_t(f) * N + y] = s;
+    if constexpr (ABS) {
+      double sa;
+      if constexpr (U16 && !WIN) {
+#pragma unroll
+        for (int o = P1 / 2; o >= 1; o >>= 1) sia += __shfl_xor(sia, o, P1);
+        sa = double(sia);
+      } else {
+#pragma unroll
+        for (int o = P1 / 2; o >= 1; o >>= 1) sda += __shfl_xor(sda, o, P1);
+        sa = sda;
+      }
+      if (j1 == 0) rowabs[int64_t(f) * N + y] = sa;
+    }
 
     // First level: DFT over j2 of z[j1 + P1 j2], twiddle W_H^{j1 k2} = W_N^{2 j1 k2}.
     dft<P2>(v);
@@ -309,16 +325,22 @@ __global__ __launch_bounds__(256) void ref_scale_kernel(int n, const double* __r
 // whose S is not positive and finite gets sigma = 0 and sets bit 0 of
 // *status. Both store 0 at k = 0 and only the stored modes (k_x <
 // row_width[r]); the pair kernel adds (sigma - sigma_ref) * refspec when it
-// reads a slot. Per-thread store offsets are computed once; the next
-// frame's columns are loaded during the second level.
-template <int N, bool REF>
+// reads a slot. SPEC (ring storage type): FP32 pairs; BF16 pairs rounded
+// once; FP16 pairs of sigma * 2^e * X with e the largest exponent for which
+// 2^e * sigma * (sum of the frame's rowabs) <= 65504, 2^-e written as
+// fscale[slot].z (1 otherwise). Per-thread store offsets are computed once;
+// the next frame's columns are loaded during the second level.
+template <int N, bool REF, int SPEC>
 __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_kernel(
     const float2* __restrict__ inter, const double* __restrict__ rowsum,
-    const double* __restrict__ refscal, float2* __restrict__ fscale, int32_t* __restrict__ status,
-    int nframes, int per_group, int64_t t0, int64_t capacity, int64_t mode_stride,
-    int64_t n_modes, const int32_t* __restrict__ row_width,
-    const int32_t* __restrict__ row_offset, const float2* __restrict__ tw,
-    float2* __restrict__ ring, float2* __restrict__ refspec) {
+    const double* __restrict__ rowabs, const double* __restrict__ refscal,
+    float4* __restrict__ fscale, int32_t* __restrict__ status, int nframes, int per_group,
+    int64_t t0, int64_t capacity, int64_t mode_stride, int64_t n_modes,
+    const int32_t* __restrict__ row_width, const int32_t* __restrict__ row_offset,
+    const float2* __restrict__ tw, char* __restrict__ ring, float2* __restrict__ refspec) {
+  static_assert(!REF || SPEC == kSpecF32, "the reference transform is kept in FP32");
+  constexpr bool F16 = SPEC == kSpecF16;
+  constexpr uint32_t MODE_BYTES = SPEC == kSpecF32 ? 8u : 4u;
   using C = ColCfg<N>;
   constexpr int P1 = C::P1, P2 = C::P2, Q = C::Q, CP = C::CP, CW = C::CW;
   constexpr int THREADS = C::THREADS, GROUPS = C::GROUPS, TILES = C::TILES;
@@ -327,6 +349,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
   __shared__ float2 lds[CW * CP];
   __shared__ float2 twl[tw_len(N)];
   __shared__ double red[NWAVES];
+  __shared__ double red_abs[F16 ? NWAVES : 1];
 
   // Workgroups are dispatched round-robin over the 8 XCDs; renumber them so
   // neighbouring column groups of a frame (which write the two halves of
@@ -372,7 +395,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
   if (CACHE && f_begin < f_end) load_cols(v, f_begin);
   float2* col_lds = lds + c * CP;
   int64_t slot = (t0 + f_begin) % capacity;
-  const uint32_t spec_bytes = uint32_t(n_modes) * 8u;
+  const uint32_t spec_bytes = uint32_t(n_modes) * MODE_BYTES;
   double s_ref = 0.0, sigma_ref = 0.0;
   if constexpr (!REF) {
     s_ref = refscal[0];
@@ -382,9 +405,12 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
 
   for (int f = f_begin; f < f_end; ++f) {
     // This thread's share of the frame's pixel sum (loads issued early).
-    double part = 0.0;
+    double part = 0.0, part_abs = 0.0;
     if constexpr (!REF) {
       for (int y = tid; y < N; y += THREADS) part += rowsum[int64_t(f) * N + y];
+    }
+    if constexpr (F16) {
+      for (int y = tid; y < N; y += THREADS) part_abs += rowabs[int64_t(f) * N + y];
     }
     if constexpr (!CACHE) load_cols(v, f);
     dft<P2>(v);
@@ -399,6 +425,11 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
       for (int o = WW / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, WW);
       if ((tid & 63) == 0) red[tid >> 6] = part;
     }
+    if constexpr (F16) {
+#pragma unroll
+      for (int o = WW / 2; o >= 1; o >>= 1) part_abs += __shfl_xor(part_abs, o, WW);
+      if ((tid & 63) == 0) red_abs[tid >> 6] = part_abs;
+    }
     __syncthreads();
     if constexpr (CACHE) {
       if (f + 1 < f_end) load_cols(v, f + 1);
@@ -412,13 +443,24 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
       const double S = s_ref + tot;
       const bool bad = !(S > 0.0) || !isfinite(S);
       const double sigma = bad ? 0.0 : double(N) * double(N) / S;
-      scale = float(sigma);
+      int e = 0;
+      if constexpr (F16) {
+        double l1 = red_abs[0];
+#pragma unroll
+        for (int w = 1; w < NWAVES; ++w) l1 += red_abs[w];
+        e = f16_exponent(sigma * l1);  // bounds every |sigma * X(k)|
+      }
+      scale = float(ldexp(sigma, e));
       if (grp == 0 && tid == 0) {
-        fscale[slot] = make_float2(float(sigma), float(sigma - sigma_ref));
+        fscale[slot] =
+            make_float4(float(sigma), float(sigma - sigma_ref), float(ldexp(1.0, -e)), 0.f);
         if (bad) atomicOr(status, 1);
       }
     }
-    const BufferRsrc dst = make_buffer(REF ? refspec : ring + slot * mode_stride, spec_bytes);
+    const BufferRsrc dst =
+        make_buffer(REF ? static_cast<void*>(refspec)
+                        : static_cast<void*>(ring + slot * mode_stride * int64_t(MODE_BYTES)),
+                    spec_bytes);
     static_for<Q>([&](auto QQ) {
       constexpr int q = decltype(QQ)::value;
       const int k2 = j1 + q * P1;
@@ -439,7 +481,13 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
         if constexpr (q == 0 && k1 == 0) {
           if (o == 0) X = make_float2(0.f, 0.f);
         }
-        buffer_store(X, dst, o);
+        if constexpr (SPEC == kSpecF32) {
+          buffer_store(X, dst, o);
+        } else {
+          // Offsets were computed for 8-byte modes; halving keeps the drop
+          // value out of range.
+          buffer_store_u32(SPEC == kSpecBF16 ? pack_bf16(X) : pack_f16(X), dst, o >> 1);
+        }
       });
     });
     if (++slot == capacity) slot = 0;
@@ -449,49 +497,67 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
 
 template <int N, typename T, bool WIN>
 hipError_t row_launch(const void* frames, const void* ref, const float* window, int nframes,
-                      float2* inter, double* rowsum, const float2* tw, hipStream_t s) {
+                      float2* inter, double* rowsum, double* rowabs, const float2* tw,
+                      hipStream_t s) {
   using C = RowCfg<N>;
   const int per = frames_per_group(nframes, C::RB);
   const int64_t blocks = int64_t(C::RB) * ((nframes + per - 1) / per);
-  hipLaunchKernelGGL((row_pass_kernel<N, T, WIN>), dim3(unsigned(blocks)), dim3(C::THREADS),
-                     0, s, static_cast<const T*>(frames), static_cast<const T*>(ref), window,
-                     nframes, per, inter, rowsum, tw);
+  if (rowabs) {
+    hipLaunchKernelGGL((row_pass_kernel<N, T, WIN, true>), dim3(unsigned(blocks)),
+                       dim3(C::THREADS), 0, s, static_cast<const T*>(frames),
+                       static_cast<const T*>(ref), window, nframes, per, inter, rowsum, rowabs,
+                       tw);
+  } else {
+    hipLaunchKernelGGL((row_pass_kernel<N, T, WIN, false>), dim3(unsigned(blocks)),
+                       dim3(C::THREADS), 0, s, static_cast<const T*>(frames),
+                       static_cast<const T*>(ref), window, nframes, per, inter, rowsum, rowabs,
+                       tw);
+  }
   return hipGetLastError();
 }
 
 template <int N>
 hipError_t row_dispatch(int in_dtype, const void* frames, const void* ref, const float* window,
-                        int nframes, float2* inter, double* rowsum, const float2* tw,
-                        hipStream_t s) {
+                        int nframes, float2* inter, double* rowsum, double* rowabs,
+                        const float2* tw, hipStream_t s) {
   if (in_dtype == 0) {
     return window ? row_launch<N, uint16_t, true>(frames, ref, window, nframes, inter, rowsum,
-                                                  tw, s)
+                                                  rowabs, tw, s)
                   : row_launch<N, uint16_t, false>(frames, ref, window, nframes, inter, rowsum,
-                                                   tw, s);
+                                                   rowabs, tw, s);
   }
-  return window ? row_launch<N, float, true>(frames, ref, window, nframes, inter, rowsum, tw, s)
-                : row_launch<N, float, false>(frames, ref, window, nframes, inter, rowsum, tw, s);
+  return window ? row_launch<N, float, true>(frames, ref, window, nframes, inter, rowsum,
+                                             rowabs, tw, s)
+                : row_launch<N, float, false>(frames, ref, window, nframes, inter, rowsum,
+                                              rowabs, tw, s);
 }
 
 template <int N>
-hipError_t col_launch(bool reference, const float2* inter, const double* rowsum, int nframes,
-                      int64_t t0, int64_t capacity, int64_t mode_stride, int64_t n_modes,
-                      const int32_t* row_width, const int32_t* row_offset, const float2* tw,
-                      float2* ring, float2* refspec, double* refscal, float2* fscale,
-                      int32_t* status, hipStream_t s) {
+hipError_t col_launch(bool reference, int spec, const float2* inter, const double* rowsum,
+                      const double* rowabs, int nframes, int64_t t0, int64_t capacity,
+                      int64_t mode_stride, int64_t n_modes, const int32_t* row_width,
+                      const int32_t* row_offset, const float2* tw, void* ring, float2* refspec,
+                      double* refscal, float4* fscale, int32_t* status, hipStream_t s) {
   using C = ColCfg<N>;
   const int per = frames_per_group(nframes, C::GROUPS);
   const int64_t blocks = int64_t(C::GROUPS) * ((nframes + per - 1) / per);
+  char* ringb = static_cast<char*>(ring);
+#define NFS_COL_GO(REFV, SPECV)                                                                \
+  hipLaunchKernelGGL((col_pass_kernel<N, REFV, SPECV>), dim3(unsigned(blocks)),               \
+                     dim3(C::THREADS), 0, s, inter, rowsum, rowabs, refscal, fscale, status,   \
+                     nframes, per, t0, capacity, mode_stride, n_modes, row_width, row_offset, \
+                     tw, ringb, refspec)
   if (reference) {
     hipLaunchKernelGGL(ref_scale_kernel, dim3(1), dim3(256), 0, s, N, rowsum, refscal, status);
-    hipLaunchKernelGGL((col_pass_kernel<N, true>), dim3(unsigned(blocks)), dim3(C::THREADS), 0,
-                       s, inter, rowsum, refscal, fscale, status, nframes, per, t0, capacity,
-                       mode_stride, n_modes, row_width, row_offset, tw, ring, refspec);
+    NFS_COL_GO(true, kSpecF32);
+  } else if (spec == kSpecBF16) {
+    NFS_COL_GO(false, kSpecBF16);
+  } else if (spec == kSpecF16) {
+    NFS_COL_GO(false, kSpecF16);
   } else {
-    hipLaunchKernelGGL((col_pass_kernel<N, false>), dim3(unsigned(blocks)), dim3(C::THREADS), 0,
-                       s, inter, rowsum, refscal, fscale, status, nframes, per, t0, capacity,
-                       mode_stride, n_modes, row_width, row_offset, tw, ring, refspec);
+    NFS_COL_GO(false, kSpecF32);
   }
+#undef NFS_COL_GO
   return hipGetLastError();
 }
 
@@ -499,10 +565,11 @@ hipError_t col_launch(bool reference, const float2* inter, const double* rowsum,
 
 hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* ref,
                            const float* window, int nframes, float2* inter, double* rowsum,
-                           const float2* tw, hipStream_t s) {
-#define NFS_ROW_CASE(NN) \
-  case NN:               \
-    return row_dispatch<NN>(in_dtype, frames, ref, window, nframes, inter, rowsum, tw, s);
+                           double* rowabs, const float2* tw, hipStream_t s) {
+#define NFS_ROW_CASE(NN)                                                                    \
+  case NN:                                                                                  \
+    return row_dispatch<NN>(in_dtype, frames, ref, window, nframes, inter, rowsum, rowabs, \
+                            tw, s);
   switch (n) {
     NFS_ROW_CASE(16)
     NFS_ROW_CASE(32)
@@ -518,16 +585,17 @@ hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* 
 #undef NFS_ROW_CASE
 }
 
-hipError_t launch_col_pass(int n, bool reference, const float2* inter, const double* rowsum,
-                           int nframes, int64_t t0, int64_t capacity, int64_t mode_stride,
-                           int64_t n_modes, const int32_t* row_width, const int32_t* row_offset,
-                           const float2* tw, float2* ring, float2* refspec, double* refscal,
-                           float2* fscale, int32_t* status, hipStream_t s) {
-#define NFS_COL_CASE(NN)                                                                  \
-  case NN:                                                                                \
-    return col_launch<NN>(reference, inter, rowsum, nframes, t0, capacity, mode_stride,  \
-                          n_modes, row_width, row_offset, tw, ring, refspec, refscal,    \
-                          fscale, status, s);
+hipError_t launch_col_pass(int n, bool reference, int spec, const float2* inter,
+                           const double* rowsum, const double* rowabs, int nframes, int64_t t0,
+                           int64_t capacity, int64_t mode_stride, int64_t n_modes,
+                           const int32_t* row_width, const int32_t* row_offset,
+                           const float2* tw, void* ring, float2* refspec, double* refscal,
+                           float4* fscale, int32_t* status, hipStream_t s) {
+#define NFS_COL_CASE(NN)                                                                   \
+  case NN:                                                                                 \
+    return col_launch<NN>(reference, spec, inter, rowsum, rowabs, nframes, t0, capacity,  \
+                          mode_stride, n_modes, row_width, row_offset, tw, ring, refspec, \
+                          refscal, fscale, status, s);
   switch (n) {
     NFS_COL_CASE(16)
     NFS_COL_CASE(32)

@@ -24,23 +24,33 @@ __global__ void bin_map_kernel(int n, int nb, int32_t* __restrict__ map) {
   }
 }
 
-// I_t = stored value + sigma_t * F[reference] on the stored modes,
-// I_t(0) = n^2, zero elsewhere.
-__global__ void expand_kernel(int n, const float2* __restrict__ spec,
+// I_t = decoded stored value + sigma_t * F[reference] on the stored modes,
+// I_t(0) = n^2, zero elsewhere. The slot holds FP32 pairs, or BF16 / FP16
+// pairs (FP16 scaled by 1 / fscale.z).
+__global__ void expand_kernel(int n, const char* __restrict__ spec_base, int spec,
                               const int32_t* __restrict__ row_width,
                               const int32_t* __restrict__ row_offset,
                               const float2* __restrict__ refspec,
-                              const float2* __restrict__ fscale_slot, float2* __restrict__ out) {
+                              const float4* __restrict__ fscale_slot, float2* __restrict__ out) {
   const int h = n / 2;
   const int64_t total = int64_t(n) * h;
-  const float sigma = fscale_slot->x;
+  const float4 sc = *fscale_slot;
+  const float sigma = sc.x;
   for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
        i += int64_t(gridDim.x) * blockDim.x) {
     const int r = int(i / h), kx = int(i % h);
     float2 v = make_float2(0.f, 0.f);
     if (kx < row_width[r]) {
       const int64_t at = row_offset[r] + kx;
-      const float2 a = spec[at], R = refspec[at];
+      float2 a;
+      if (spec == dev::kSpecF32) {
+        a = reinterpret_cast<const float2*>(spec_base)[at];
+      } else {
+        const uint32_t w = reinterpret_cast<const uint32_t*>(spec_base)[at];
+        a = spec == dev::kSpecBF16 ? dev::unpack_bf16(w) : dev::unpack_f16(w);
+        a = make_float2(a.x * sc.z, a.y * sc.z);
+      }
+      const float2 R = refspec[at];
       v = make_float2(fmaf(sigma, R.x, a.x), fmaf(sigma, R.y, a.y));
       if (at == 0) v = make_float2(float(n) * float(n), 0.f);
     }
@@ -98,13 +108,14 @@ hipError_t launch_bin_map(int n, int n_bins, int32_t* map, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_expand_spectrum(int n, const float2* ring, int64_t slot, int64_t mode_stride,
-                                  const int32_t* row_width, const int32_t* row_offset,
-                                  const float2* refspec, const float2* fscale, float2* out,
-                                  hipStream_t s) {
+hipError_t launch_expand_spectrum(int n, const void* ring, int spec, int64_t slot,
+                                  int64_t mode_stride, const int32_t* row_width,
+                                  const int32_t* row_offset, const float2* refspec,
+                                  const float4* fscale, float2* out, hipStream_t s) {
+  const int64_t mode_bytes = spec == dev::kSpecF32 ? 8 : 4;
+  const char* base = static_cast<const char*>(ring) + slot * mode_stride * mode_bytes;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_for(int64_t(n) * (n / 2), 256)), dim3(256), 0, s,
-                     n, ring + slot * mode_stride, row_width, row_offset, refspec, fscale + slot,
-                     out);
+                     n, base, spec, row_width, row_offset, refspec, fscale + slot, out);
   return hipGetLastError();
 }
 

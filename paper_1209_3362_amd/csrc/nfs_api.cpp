@@ -25,15 +25,16 @@ struct nfs_plan_s {
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   const float* window = nullptr;
-  float2* ring = nullptr;
+  void* ring = nullptr;         // capacity slots of mode_stride stored modes
   float2* inter = nullptr;
   double* rowsum = nullptr;
+  double* rowabs = nullptr;     // row sums of |frame - reference| (FP16 storage)
   float* acc = nullptr;
   int32_t* status = nullptr;    // bit 0: a degenerate frame was pushed
   double* refscal = nullptr;    // {S_ref, sigma_ref} of the reference frame
   void* ref = nullptr;          // reference frame: first frame of the sequence
   float2* refspec = nullptr;    // its transform on the stored modes
-  float2* fscale = nullptr;     // per ring slot: {sigma, sigma - sigma_ref}
+  float4* fscale = nullptr;     // per ring slot: {sigma, sigma - sigma_ref, 2^-e, 0}
   int32_t* seg_bin = nullptr;   // binning segments (see nfs::Layout)
   int32_t* seg_row0 = nullptr;
   int32_t* bin_seg0 = nullptr;
@@ -75,7 +76,8 @@ nfs_status flush_pairs(nfs_plan_s* h) {
   if (h->t_done >= h->t_pushed) return NFS_OK;
   const nfs::Layout& L = h->L;
   for (const nfs::LagGroup& g : L.groups) {
-    hipError_t e = nfs::launch_pairs(h->ring, h->refspec, h->fscale, L.modes, L.mode_stride,
+    hipError_t e = nfs::launch_pairs(h->ring, L.spec_dtype, L.accum == NFS_ACC_KAHAN,
+                                     h->refspec, h->fscale, L.modes, L.mode_stride,
                                      L.capacity, h->t_done,
                                      h->t_pushed, h->lags + g.first, g.count, g.max_lag,
                                      h->acc + g.first, L.n_lags, g.modes, g.hist, g.waves,
@@ -146,9 +148,11 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->stream = static_cast<hipStream_t>(stream);
   h->ws = static_cast<char*>(workspace);
   h->window = desc->window;
-  h->ring = reinterpret_cast<float2*>(h->ws + L.off_ring);
+  h->ring = h->ws + L.off_ring;
   h->inter = reinterpret_cast<float2*>(h->ws + L.off_inter);
   h->rowsum = reinterpret_cast<double*>(h->ws + L.off_rowsum);
+  h->rowabs = L.spec_dtype == NFS_SPEC_F16 ? reinterpret_cast<double*>(h->ws + L.off_rowabs)
+                                            : nullptr;
   h->acc = reinterpret_cast<float*>(h->ws + L.off_acc);
   h->status = reinterpret_cast<int32_t*>(h->ws + L.off_status);
   h->tw = reinterpret_cast<float2*>(h->ws + L.off_tw);
@@ -158,7 +162,7 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->refscal = reinterpret_cast<double*>(h->ws + L.off_status + 8);
   h->ref = h->ws + L.off_ref;
   h->refspec = reinterpret_cast<float2*>(h->ws + L.off_refspec);
-  h->fscale = reinterpret_cast<float2*>(h->ws + L.off_fscale);
+  h->fscale = reinterpret_cast<float4*>(h->ws + L.off_fscale);
   const size_t nseg = L.seg_bin.size();
   h->seg_bin = reinterpret_cast<int32_t*>(h->ws + L.off_segs);
   h->seg_row0 = h->seg_bin + nseg;
@@ -241,19 +245,21 @@ nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count) {
       e = hipMemcpyAsync(h->ref, src, frame_bytes, hipMemcpyDeviceToDevice, h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "reference copy");
       e = nfs::launch_row_pass(L.n, L.in_dtype, h->ref, nullptr, h->window, 1, h->inter,
-                               h->rowsum, h->tw, h->stream);
+                               h->rowsum, nullptr, h->tw, h->stream);
       if (e == hipSuccess)
-        e = nfs::launch_col_pass(L.n, true, h->inter, h->rowsum, 1, 0, L.capacity,
-                                 L.mode_stride, L.modes, h->width, h->offset, h->tw, h->ring,
-                                 h->refspec, h->refscal, h->fscale, h->status, h->stream);
+        e = nfs::launch_col_pass(L.n, true, NFS_SPEC_F32, h->inter, h->rowsum, nullptr, 1, 0,
+                                 L.capacity, L.mode_stride, L.modes, h->width, h->offset, h->tw,
+                                 h->ring, h->refspec, h->refscal, h->fscale, h->status,
+                                 h->stream);
       if (e != hipSuccess) return hip_fail(h, e, "reference transform launch");
     }
     e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->ref, h->window, int(b), h->inter,
-                             h->rowsum, h->tw, h->stream);
+                             h->rowsum, h->rowabs, h->tw, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
-    e = nfs::launch_col_pass(L.n, false, h->inter, h->rowsum, int(b), h->t_pushed, L.capacity,
-                             L.mode_stride, L.modes, h->width, h->offset, h->tw, h->ring,
-                             h->refspec, h->refscal, h->fscale, h->status, h->stream);
+    e = nfs::launch_col_pass(L.n, false, L.spec_dtype, h->inter, h->rowsum, h->rowabs, int(b),
+                             h->t_pushed, L.capacity, L.mode_stride, L.modes, h->width,
+                             h->offset, h->tw, h->ring, h->refspec, h->refscal, h->fscale,
+                             h->status, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
     h->t_pushed += b;
     i += b;
@@ -332,10 +338,10 @@ nfs_status nfs_copy_spectrum(nfs_handle h, int64_t t, float* out) {
   if (!out) return fail(h, NFS_E_ARG, "out is NULL");
   if (t < 0 || t >= h->t_pushed || t < h->t_pushed - h->L.capacity)
     return fail(h, NFS_E_STATE, "frame is not in the ring");
-  hipError_t e = nfs::launch_expand_spectrum(h->L.n, h->ring, t % h->L.capacity,
-                                             h->L.mode_stride, h->width, h->offset, h->refspec,
-                                             h->fscale, reinterpret_cast<float2*>(out),
-                                             h->stream);
+  hipError_t e = nfs::launch_expand_spectrum(h->L.n, h->ring, h->L.spec_dtype,
+                                             t % h->L.capacity, h->L.mode_stride, h->width,
+                                             h->offset, h->refspec, h->fscale,
+                                             reinterpret_cast<float2*>(out), h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "expand launch");
   return NFS_OK;
 }

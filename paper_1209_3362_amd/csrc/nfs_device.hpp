@@ -35,6 +35,46 @@ __device__ __forceinline__ BufferRsrc make_buffer(void* base, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(base, static_cast<short>(0), static_cast<int>(bytes),
                                            kBufferWord3);
 }
+__device__ __forceinline__ void buffer_store_u32(uint32_t v, BufferRsrc r, uint32_t byte_offset) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, static_cast<int>(byte_offset), 0, 0);
+}
+
+// Storage types of the resident spectra (values of nfs_desc.spec_dtype).
+constexpr int kSpecF32 = 0, kSpecBF16 = 1, kSpecF16 = 2;
+
+// (re, im) rounded to BF16 / FP16 (nearest, ties to even), re in the low
+// half of the word.
+__device__ __forceinline__ uint32_t pack_bf16(float2 v) {
+  const __bf16 a = static_cast<__bf16>(v.x), b = static_cast<__bf16>(v.y);
+  return uint32_t(__builtin_bit_cast(uint16_t, a)) |
+         (uint32_t(__builtin_bit_cast(uint16_t, b)) << 16);
+}
+__device__ __forceinline__ uint32_t pack_f16(float2 v) {
+  const _Float16 a = static_cast<_Float16>(v.x), b = static_cast<_Float16>(v.y);
+  return uint32_t(__builtin_bit_cast(uint16_t, a)) |
+         (uint32_t(__builtin_bit_cast(uint16_t, b)) << 16);
+}
+// Inverses (exact).
+__device__ __forceinline__ float2 unpack_bf16(uint32_t w) {
+  return make_float2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u));
+}
+__device__ __forceinline__ float2 unpack_f16(uint32_t w) {
+  return make_float2(static_cast<float>(__builtin_bit_cast(_Float16, uint16_t(w & 0xffffu))),
+                     static_cast<float>(__builtin_bit_cast(_Float16, uint16_t(w >> 16))));
+}
+
+// Largest e with bound * 2^e <= 65504 (the FP16 maximum), 0 for a bound
+// that is not positive and finite, clamped to [-100, 100].
+__device__ __forceinline__ int f16_exponent(double bound) {
+  if (!(bound > 0.0) || !isfinite(bound)) return 0;
+  int k = 0;
+  (void)frexp(65504.0 / bound, &k);
+  int e = k - 1;
+  while (e > -100 && ldexp(bound, e) > 65504.0) --e;
+  while (e < 100 && ldexp(bound, e + 1) <= 65504.0) ++e;
+  return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+
 __device__ __forceinline__ void buffer_store(float2 v, BufferRsrc r, uint32_t byte_offset) {
   using U2 = __attribute__((ext_vector_type(2))) unsigned;
   U2 bits;

@@ -44,10 +44,11 @@ nfs_status validate_desc(const nfs_desc* d, std::string* err) {
     return fail(NFS_E_SIZE, "n must be a power of two in [16, 4096]");
   if (d->in_dtype != NFS_IN_U16 && d->in_dtype != NFS_IN_F32)
     return fail(NFS_E_ARG, "in_dtype must be NFS_IN_U16 or NFS_IN_F32");
-  if (d->spec_dtype != NFS_SPEC_F32)
-    return fail(NFS_E_UNSUPPORTED, "only NFS_SPEC_F32 spectra are implemented");
-  if (d->accum != NFS_ACC_PLAIN)
-    return fail(NFS_E_UNSUPPORTED, "only NFS_ACC_PLAIN accumulation is implemented");
+  if (d->spec_dtype != NFS_SPEC_F32 && d->spec_dtype != NFS_SPEC_BF16 &&
+      d->spec_dtype != NFS_SPEC_F16)
+    return fail(NFS_E_UNSUPPORTED, "spec_dtype must be NFS_SPEC_F32, _BF16 or _F16");
+  if (d->accum != NFS_ACC_PLAIN && d->accum != NFS_ACC_KAHAN)
+    return fail(NFS_E_UNSUPPORTED, "accum must be NFS_ACC_PLAIN or NFS_ACC_KAHAN");
   if (d->n_lags < 1 || !d->lags) return fail(NFS_E_LAGS, "need at least one lag");
   for (int i = 0; i < d->n_lags; ++i) {
     if (d->lags[i] < 0) return fail(NFS_E_LAGS, "lags must be >= 0");
@@ -132,6 +133,9 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.n_bins = d->n_bins;
   o.n_lags = d->n_lags;
   o.in_dtype = d->in_dtype;
+  o.spec_dtype = d->spec_dtype;
+  o.accum = d->accum;
+  o.mode_bytes = d->spec_dtype == NFS_SPEC_F32 ? 8 : 4;
   o.lags.assign(d->lags, d->lags + d->n_lags);
   o.max_lag = o.lags.back();
 
@@ -190,6 +194,8 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   };
   o.off_inter = take(size_t(o.batch) * inter_frame);
   o.off_rowsum = take(size_t(o.batch) * o.n * 8);
+  // Row sums of |frame - reference|, for the FP16 scale only.
+  o.off_rowabs = take(o.spec_dtype == NFS_SPEC_F16 ? size_t(o.batch) * o.n * 8 : 0);
   o.off_acc = take(size_t(o.n_lags) * o.mode_stride * 4);
   const size_t nseg = o.seg_bin.size();
   o.off_segs = take((2 * nseg + o.bin_seg0.size()) * 4);
@@ -203,10 +209,10 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_ref = take(size_t(o.n) * o.n * (o.in_dtype == NFS_IN_U16 ? 2 : 4));
   o.off_refspec = take(size_t(o.mode_stride) * 8);
   o.off_ring = off;
-  // Each ring slot holds one spectrum and, after the ring, its frame's
-  // scales; spectra are whole multiples of kAlign bytes.
-  const size_t spec_bytes = size_t(o.mode_stride) * 8;
-  const size_t slot_bytes = spec_bytes + 8;
+  // Each ring slot holds one spectrum (8 or 4 bytes per mode, whole
+  // multiples of kAlign bytes) and, after the ring, its frame's scales.
+  const size_t spec_bytes = size_t(o.mode_stride) * o.mode_bytes;
+  const size_t slot_bytes = spec_bytes + kScaleBytes;
 
   if (d->capacity > 0) {
     o.capacity = d->capacity;
@@ -225,7 +231,7 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
     return NFS_E_CAPACITY;
   }
   o.off_fscale = o.off_ring + size_t(o.capacity) * spec_bytes;
-  o.total = align_up(o.off_fscale + size_t(o.capacity) * 8, kAlign);
+  o.total = align_up(o.off_fscale + size_t(o.capacity) * kScaleBytes, kAlign);
   return NFS_OK;
 }
 

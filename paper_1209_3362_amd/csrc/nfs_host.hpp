@@ -36,6 +36,8 @@ constexpr size_t kBatchBytes = size_t(128) << 20;
 constexpr int kMaxBatch = 1024;
 // Most ring slots (slot indices are 32-bit in the kernels).
 constexpr int64_t kMaxCapacity = 0x7fffffff;
+// Per ring slot: {sigma, sigma - sigma_ref, 2^-e (FP16 storage, else 1), 0}.
+constexpr size_t kScaleBytes = 16;
 
 inline bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -70,6 +72,8 @@ struct LagGroup {
 struct Layout {
   int n = 0, h = 0, n_bins = 0, n_lags = 0;
   int in_dtype = 0;
+  int spec_dtype = 0, accum = 0;
+  int mode_bytes = 8;      // bytes per stored mode in the ring
   int64_t modes = 0;       // M: stored modes per spectrum
   int64_t mode_stride = 0; // M rounded up to 64: ring slot and sum-row pitch
   int64_t capacity = 0;    // ring slots
@@ -84,10 +88,10 @@ struct Layout {
   // [bin_seg0[b], bin_seg0[b + 1]).
   std::vector<int32_t> seg_bin, seg_row0, bin_seg0;
   // Byte offsets into the workspace.
-  size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_acc = 0;
+  size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_rowabs = 0, off_acc = 0;
   size_t off_status = 0, off_tw = 0, off_width = 0, off_offset = 0;
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
-  size_t off_fscale = 0;  // after the ring: per slot {sigma, sigma - sigma_ref}
+  size_t off_fscale = 0;  // after the ring: kScaleBytes per slot
   size_t off_segs = 0, off_part = 0, off_part_cnt = 0;
   size_t off_lags = 0, total = 0;
 };

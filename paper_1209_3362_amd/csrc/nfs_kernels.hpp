@@ -13,37 +13,44 @@ namespace nfs {
 // transformed. frames: [nframes][n][n] of u16 (in_dtype 0) or f32 (1);
 // ref: [n][n] of the same type subtracted from every frame first, or null;
 // window: [n][n] multiplied in after the subtraction, or null. Writes inter
-// [nframes][n/4][n][2] complex (2-column tiles) and rowsum [nframes][n].
+// [nframes][n/4][n][2] complex (2-column tiles), rowsum [nframes][n] and,
+// when rowabs is not null, rowabs [nframes][n]: the rows' sums of |what was
+// transformed|.
 hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* ref,
                            const float* window, int nframes, float2* inter, double* rowsum,
-                           const float2* tw, hipStream_t s);
+                           double* rowabs, const float2* tw, hipStream_t s);
 
 // Column pass (per column k_x: complex transform over the n rows), with the
 // frame scales formed from the row sums.
 // reference == true: the rows are the reference image (one frame); set
 // refscal = {S_ref, n^2/S_ref} and store its transform unscaled in refspec
-// (0 at k = 0).
+// (FP32, 0 at k = 0).
 // reference == false: the rows are (frame - reference); with
-// sigma = n^2 / (S_ref + row sums), fscale[slot] = {sigma, sigma - sigma_ref}
-// and sigma * X, 0 at k = 0, stored for frame f in ring slot
-// slot = (t0 + f) mod capacity. A frame whose sum is not positive and finite
-// sets bit 0 of *status and gets sigma = 0. n_modes: stored modes per
-// spectrum; only those are written.
-hipError_t launch_col_pass(int n, bool reference, const float2* inter, const double* rowsum,
-                           int nframes, int64_t t0, int64_t capacity, int64_t mode_stride,
-                           int64_t n_modes, const int32_t* row_width, const int32_t* row_offset,
-                           const float2* tw, float2* ring, float2* refspec, double* refscal,
-                           float2* fscale, int32_t* status, hipStream_t s);
+// sigma = n^2 / (S_ref + row sums), store sigma * X, 0 at k = 0, for frame f
+// in ring slot slot = (t0 + f) mod capacity in the storage type `spec`
+// (nfs_desc.spec_dtype: 8 or 4 bytes per mode, mode_stride modes per slot),
+// and fscale[slot] = {sigma, sigma - sigma_ref, 2^-e, 0}, with e the FP16
+// scale exponent formed from rowabs (FP16 storage) or 0. A frame whose sum
+// is not positive and finite sets bit 0 of *status and gets sigma = 0.
+// n_modes: stored modes per spectrum; only those are written.
+hipError_t launch_col_pass(int n, bool reference, int spec, const float2* inter,
+                           const double* rowsum, const double* rowabs, int nframes, int64_t t0,
+                           int64_t capacity, int64_t mode_stride, int64_t n_modes,
+                           const int32_t* row_width, const int32_t* row_offset,
+                           const float2* tw, void* ring, float2* refspec, double* refscal,
+                           float4* fscale, int32_t* status, hipStream_t s);
 
 // Lag-pair accumulation for target frames [T0, T1) and the lags
 // lags[0..n_lags): acc[m * acc_pitch + l] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2
 // over t in [T0, T1) with t - lag >= 0 (acc is mode-major), where
-// I_t = ring slot of t + fscale[slot].y * refspec (refspec has mode_stride
-// entries, 0 at k = 0). Frames [max(0, T0 - max lag), T1) must be in the
-// ring. `modes` per workgroup (16 or 8), `hist` LDS rows; wave w
-// sums lags [w * per_wave, (w + 1) * per_wave) (per_wave <= kMaxLagsPerWave).
-hipError_t launch_pairs(const float2* ring, const float2* refspec, const float2* fscale,
-                        int64_t n_modes, int64_t mode_stride,
+// I_t = decoded ring slot of t + fscale[slot].y * refspec (refspec has
+// mode_stride entries, 0 at k = 0; the ring stores `spec`-typed modes,
+// FP16 ones scaled by 1 / fscale[slot].z). Frames [max(0, T0 - max lag), T1)
+// must be in the ring. `modes` per workgroup (16 or 8), `hist` LDS rows;
+// wave w sums lags of a near-equal contiguous slice (at most per_wave);
+// kahan: chunk sums added with Kahan compensation.
+hipError_t launch_pairs(const void* ring, int spec, bool kahan, const float2* refspec,
+                        const float4* fscale, int64_t n_modes, int64_t mode_stride,
                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                         int n_lags, int max_lag, float* acc, int acc_pitch, int modes, int hist,
                         int waves, int per_wave, size_t lds, hipStream_t s);
@@ -66,13 +73,13 @@ hipError_t launch_fill_u32(void* dst, size_t words, uint32_t value, hipStream_t 
 // Writes the bin of every half-plane mode to map [n][n/2].
 hipError_t launch_bin_map(int n, int n_bins, int32_t* map, hipStream_t s);
 
-// Expands ring slot `slot` to the spectrum out [n][n/2] complex: stored
-// value + sigma * refspec (sigma = fscale[slot].x), I(0) = n^2, zeros where
-// not stored.
-hipError_t launch_expand_spectrum(int n, const float2* ring, int64_t slot,
+// Expands ring slot `slot` to the spectrum out [n][n/2] complex: decoded
+// stored value + sigma * refspec (sigma = fscale[slot].x), I(0) = n^2,
+// zeros where not stored.
+hipError_t launch_expand_spectrum(int n, const void* ring, int spec, int64_t slot,
                                   int64_t mode_stride, const int32_t* row_width,
                                   const int32_t* row_offset, const float2* refspec,
-                                  const float2* fscale, float2* out, hipStream_t s);
+                                  const float4* fscale, float2* out, hipStream_t s);
 
 // P_tau(k) = acc[mode][l] / (n_frames - lags[l]) written to out
 // [n_lags][n][n/2 + 1] (0 at modes that are not stored, NaN for every mode

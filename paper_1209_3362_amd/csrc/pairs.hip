@@ -28,15 +28,23 @@
 
 namespace nfs {
 namespace {
+using dev::kSpecBF16;
+using dev::kSpecF32;
+using dev::unpack_bf16;
+using dev::unpack_f16;
 
 // K modes per workgroup, MAXLW lag slots per wave, NW waves launched: the
 // lag list is split into lag_waves <= NW contiguous slices of near-equal
 // length, one per wave; slots past a slice's end read harmless rows and are
-// not summed. NW = 8 leaves each wave 256 registers, NW = 12 170.
-template <int K, int MAXLW, int NW>
+// not summed. NW = 8 leaves each wave 256 registers, NW = 12 170. KAHAN: each
+// lag's terms of a chunk are summed in FP32 and the chunk sums added with
+// Kahan compensation. `spec` is the ring's storage type (uniform): FP32
+// pairs, or BF16 / FP16 pairs decoded (and FP16 scaled by fscale[slot].z)
+// as a slot is copied into LDS.
+template <int K, int MAXLW, int NW, bool KAHAN>
 __global__ __launch_bounds__(64 * NW) void pair_kernel(
-    const float2* __restrict__ ring, const float2* __restrict__ refspec,
-    const float2* __restrict__ fscale, int64_t n_modes, int64_t mode_stride, int64_t capacity,
+    const char* __restrict__ ring, int spec, const float2* __restrict__ refspec,
+    const float4* __restrict__ fscale, int64_t n_modes, int64_t mode_stride, int64_t capacity,
     int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags, int max_lag,
     float* __restrict__ acc, int acc_pitch, int H, int lag_waves) {
   static_assert(K == 16 || K == 8, "16 or 8 modes per workgroup");
@@ -81,10 +89,26 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
   for (int s = 1; s < MAXLW; ++s)
     if (s < l_count && tau[s] != tau[0] + s) consecutive = false;
 
-  // Window offset u lives in LDS row (u + max_lag) mod H.
-  auto slot_row = [&](int64_t slot) -> const float4* {
-    return reinterpret_cast<const float4*>(ring + slot * mode_stride + m0);
+  // Ring slot bytes and the two modes m0 + 2 col2, m0 + 2 col2 + 1 of a slot:
+  // one float4 (FP32) or one 8-byte word pair (16-bit storage), kept raw in
+  // a float4 until decoded.
+  const bool f32 = spec == kSpecF32;
+  const int64_t mode_bytes = f32 ? 8 : 4;
+  const int64_t slot_bytes = mode_stride * mode_bytes;
+  const char* ring_m0 = ring + m0 * mode_bytes;
+  auto load_raw = [&](const char* p) -> float4 {
+    if (f32) return *reinterpret_cast<const float4*>(p);
+    const uint2 w = *reinterpret_cast<const uint2*>(p);
+    return make_float4(__uint_as_float(w.x), __uint_as_float(w.y), 0.f, 0.f);
   };
+  auto decode = [&](float4 raw, float inv_scale) -> float4 {
+    if (f32) return raw;
+    const uint32_t w0 = __float_as_uint(raw.x), w1 = __float_as_uint(raw.y);
+    const float2 a = spec == kSpecBF16 ? unpack_bf16(w0) : unpack_f16(w0);
+    const float2 b = spec == kSpecBF16 ? unpack_bf16(w1) : unpack_f16(w1);
+    return make_float4(a.x * inv_scale, a.y * inv_scale, b.x * inv_scale, b.y * inv_scale);
+  };
+  // Window offset u lives in LDS row (u + max_lag) mod H.
   auto put_row = [&](int row, int col2, float4 val) {
     hist4[(row * K) / 2 + col2] = val;
     if (row < MR) hist4[((row + H) * K) / 2 + col2] = val;
@@ -109,9 +133,9 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
       const int r = e / V4, col2 = e % V4;
       int slot = slot0 + r;
       if (slot >= cap0) slot -= cap0;
-      const float4 v = slot_row(slot)[col2];
-      const float d = fscale[slot].y;
-      put_row((max_lag - pre + r) % H, col2, corrected(v, d, ref4[col2]));
+      const float4 raw = load_raw(ring_m0 + slot * slot_bytes + col2 * 2 * mode_bytes);
+      const float4 sc = fscale[slot];
+      put_row((max_lag - pre + r) % H, col2, corrected(decode(raw, sc.z), sc.y, ref4[col2]));
     };
     int e = threadIdx.x;
     for (; e + 3 * nthreads < total; e += 4 * nthreads) {
@@ -125,14 +149,13 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
   // waves take part or not), so its two modes' reference values stay in
   // registers. Slot arithmetic is 32-bit (capacity < 2^31).
   const int cap = int(capacity);
-  const uint32_t stride4 = uint32_t(mode_stride / 2);  // float4 per ring slot
   const int n_el = S * V4;
   const bool loader = int(threadIdx.x) < n_el;
   const int pdt = int(threadIdx.x) / V4, pcol = int(threadIdx.x) % V4;
-  const float4* pbase = reinterpret_cast<const float4*>(ring + m0) + pcol;
+  const char* pbase = ring_m0 + pcol * 2 * mode_bytes;
   const float4 rr = loader ? ref4[pcol] : make_float4(0.f, 0.f, 0.f, 0.f);
   float4 pf = make_float4(0.f, 0.f, 0.f, 0.f);
-  float pd = 0.f;
+  float pd = 0.f, ps = 1.f;
   // Rows of the chunk at window offset c, starting in ring slot cslot. A
   // row past the window end loads the chunk's first slot instead (only
   // masked targets ever meet it); every other row is a frame of the window
@@ -144,43 +167,71 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
       const uint32_t dt = uint32_t(c) + updt < ulen ? updt : 0u;
       uint32_t slot = uint32_t(cslot) + dt;
       slot = slot >= ucap ? slot - ucap : slot;
-      pf = pbase[size_t(slot) * stride4];
-      pd = fscale[slot].y;
+      pf = load_raw(pbase + size_t(slot) * size_t(slot_bytes));
+      const float4 sc = fscale[slot];
+      pd = sc.y;
+      ps = sc.z;
     }
   };
   auto commit = [&](int crow) {
     if (loader) {
       int row = crow + pdt;
       if (row >= H) row -= H;
-      put_row(row, pcol, corrected(pf, pd, rr));
+      put_row(row, pcol, corrected(decode(pf, ps), pd, rr));
     }
   };
 
+  // Plain: running sums of dx^2 (ax) and dy^2 (ay). KAHAN: running sum
+  // (ax) and compensation (ay) of the chunk sums.
   float ax[MAXLW], ay[MAXLW];
 #pragma unroll
   for (int s = 0; s < MAXLW; ++s) ax[s] = ay[s] = 0.f;
+  auto add_chunk = [&](int s, float v) {
+    const float y = v - ay[s];
+    const float t = ax[s] + y;
+    ay[s] = (t - ax[s]) - y;
+    ax[s] = t;
+  };
 
   // |cur[i] - old[i]|^2 into lag slot s.
   auto acc_plain = [&](const float2* cur, const float2* old, int s) {
+    if constexpr (KAHAN) {
+      float px = 0.f, py = 0.f;
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-      const float dx = cur[i].x - old[i].x, dy = cur[i].y - old[i].y;
-      ax[s] = fmaf(dx, dx, ax[s]);
-      ay[s] = fmaf(dy, dy, ay[s]);
+      for (int i = 0; i < RPT; ++i) {
+        const float dx = cur[i].x - old[i].x, dy = cur[i].y - old[i].y;
+        px = fmaf(dx, dx, px);
+        py = fmaf(dy, dy, py);
+      }
+      add_chunk(s, px + py);
+    } else {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const float dx = cur[i].x - old[i].x, dy = cur[i].y - old[i].y;
+        ax[s] = fmaf(dx, dx, ax[s]);
+        ay[s] = fmaf(dy, dy, ay[s]);
+      }
     }
   };
   // The same with targets that have no partner yet (u < first) or lie past
   // the window end zeroed by selects, not branches.
   auto acc_masked = [&](const float2* cur, const float2* old, int s, int ub) {
+    float px = 0.f, py = 0.f;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
       const int u = ub + i;
       const bool ok = (u >= first[s]) & (u < len);
       const float dx = ok ? cur[i].x - old[i].x : 0.f;
       const float dy = ok ? cur[i].y - old[i].y : 0.f;
-      ax[s] = fmaf(dx, dx, ax[s]);
-      ay[s] = fmaf(dy, dy, ay[s]);
+      if constexpr (KAHAN) {
+        px = fmaf(dx, dx, px);
+        py = fmaf(dy, dy, py);
+      } else {
+        ax[s] = fmaf(dx, dx, ax[s]);
+        ay[s] = fmaf(dy, dy, ay[s]);
+      }
     }
+    if constexpr (KAHAN) add_chunk(s, px + py);
   };
   int first_max = 0;
 #pragma unroll
@@ -339,7 +390,7 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
 #pragma unroll
   for (int s = 0; s < MAXLW; ++s) {
     if (s < l_count) {
-      float v = ax[s] + ay[s];
+      float v = KAHAN ? ax[s] - ay[s] : ax[s] + ay[s];
 #pragma unroll
       for (int o = K; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
       if (g == 0) blk[m * n_lags + l_begin + s] = v;
@@ -354,34 +405,34 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
   }
 }
 
-template <int K, int P, int NW>
-hipError_t pair_launch(const float2* ring, const float2* refspec, const float2* fscale,
+template <int K, int P, int NW, bool KAHAN>
+hipError_t pair_launch(const char* ring, int spec, const float2* refspec, const float4* fscale,
                        int64_t n_modes, int64_t mode_stride, int64_t capacity, int64_t T0,
                        int64_t T1, const int32_t* lags, int n_lags, int max_lag, float* acc,
                        int acc_pitch, int hist, int waves, size_t lds, hipStream_t s) {
   // Allow the LDS history beyond the default dynamic limit; a failure here
   // shows up as a launch error below.
-  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_kernel<K, P, NW>),
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_kernel<K, P, NW, KAHAN>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
   const int64_t blocks = (n_modes + K - 1) / K;
-  hipLaunchKernelGGL((pair_kernel<K, P, NW>), dim3(unsigned(blocks)), dim3(64 * NW), lds, s,
-                     ring, refspec, fscale, n_modes, mode_stride, capacity, T0, T1, lags, n_lags,
-                     max_lag, acc, acc_pitch, hist, waves);
+  hipLaunchKernelGGL((pair_kernel<K, P, NW, KAHAN>), dim3(unsigned(blocks)), dim3(64 * NW), lds,
+                     s, ring, spec, refspec, fscale, n_modes, mode_stride, capacity, T0, T1,
+                     lags, n_lags, max_lag, acc, acc_pitch, hist, waves);
   return hipGetLastError();
 }
 
 // Up to 8 lag waves run in 8-wave workgroups; more (only with 6 or more
 // lags per wave) in 12-wave ones.
-template <int K>
-hipError_t pair_dispatch(int per_wave, const float2* ring, const float2* refspec,
-                         const float2* fscale, int64_t n_modes, int64_t mode_stride,
+template <int K, bool KAHAN>
+hipError_t pair_dispatch(int per_wave, const char* ring, int spec, const float2* refspec,
+                         const float4* fscale, int64_t n_modes, int64_t mode_stride,
                          int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                          int n_lags, int max_lag, float* acc, int acc_pitch, int hist, int waves,
                          size_t lds, hipStream_t s) {
-#define NFS_PAIR_P(PP, NWW)                                                                \
-  return pair_launch<K, PP, NWW>(ring, refspec, fscale, n_modes, mode_stride, capacity,   \
-                                 T0, T1, lags, n_lags, max_lag, acc, acc_pitch, hist,       \
-                                 waves, lds, s)
+#define NFS_PAIR_P(PP, NWW)                                                                 \
+  return pair_launch<K, PP, NWW, KAHAN>(ring, spec, refspec, fscale, n_modes, mode_stride, \
+                                        capacity, T0, T1, lags, n_lags, max_lag, acc,       \
+                                        acc_pitch, hist, waves, lds, s)
   if (waves <= 8) {
     switch (per_wave) {
       case 1: NFS_PAIR_P(1, 8);
@@ -409,21 +460,25 @@ hipError_t pair_dispatch(int per_wave, const float2* ring, const float2* refspec
 
 }  // namespace
 
-hipError_t launch_pairs(const float2* ring, const float2* refspec, const float2* fscale,
-                        int64_t n_modes, int64_t mode_stride,
+hipError_t launch_pairs(const void* ring, int spec, bool kahan, const float2* refspec,
+                        const float4* fscale, int64_t n_modes, int64_t mode_stride,
                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                         int n_lags, int max_lag, float* acc, int acc_pitch, int modes, int hist,
                         int waves, int per_wave, size_t lds, hipStream_t s) {
-#define NFS_PAIR_CASE(KK)                                                                  \
-  case KK:                                                                                 \
-    return pair_dispatch<KK>(per_wave, ring, refspec, fscale, n_modes, mode_stride,        \
-                             capacity, T0, T1, lags, n_lags, max_lag, acc, acc_pitch, hist, \
-                             waves, lds, s);
-  switch (modes) {
-    NFS_PAIR_CASE(16)
-    NFS_PAIR_CASE(8)
-    default: return hipErrorInvalidValue;
+  const char* r = static_cast<const char*>(ring);
+#define NFS_PAIR_CASE(KK, KH)                                                              \
+  return pair_dispatch<KK, KH>(per_wave, r, spec, refspec, fscale, n_modes, mode_stride,  \
+                               capacity, T0, T1, lags, n_lags, max_lag, acc, acc_pitch,   \
+                               hist, waves, lds, s)
+  if (modes == 16) {
+    if (kahan) NFS_PAIR_CASE(16, true);
+    NFS_PAIR_CASE(16, false);
   }
+  if (modes == 8) {
+    if (kahan) NFS_PAIR_CASE(8, true);
+    NFS_PAIR_CASE(8, false);
+  }
+  return hipErrorInvalidValue;
 #undef NFS_PAIR_CASE
 }
 

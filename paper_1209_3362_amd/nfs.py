@@ -17,6 +17,8 @@ STATUS = {
     8: "NFS_E_DEGENERATE_FRAME", 9: "NFS_E_HIP", 10: "NFS_E_UNSUPPORTED",
 }
 IN_DTYPES = {"u16": 0, "f32": 1}
+SPEC_DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+ACCUMS = {"plain": 0, "kahan": 1}
 NFS_OK = 0
 NFS_E_DEGENERATE_FRAME = 8
 
@@ -86,18 +88,20 @@ def load_library():
     return lib
 
 
-def _desc(n, lags, n_bins, in_dtype, capacity, window_ptr):
+def _desc(n, lags, n_bins, in_dtype, capacity, window_ptr, spec="f32", accum="plain"):
     arr = (ctypes.c_int32 * len(lags))(*[int(t) for t in lags])
-    d = NfsDesc(n=int(n), in_dtype=IN_DTYPES[in_dtype], spec_dtype=0, accum=0,
+    d = NfsDesc(n=int(n), in_dtype=IN_DTYPES[in_dtype], spec_dtype=SPEC_DTYPES[spec],
+                accum=ACCUMS[accum],
                 n_lags=len(lags), lags=arr, n_bins=int(n_bins),
                 capacity=int(capacity), window=window_ptr)
     return d, arr
 
 
-def workspace_size(n, lags, n_bins, in_dtype="u16", capacity=0, window=False):
+def workspace_size(n, lags, n_bins, in_dtype="u16", capacity=0, window=False, spec="f32",
+                   accum="plain"):
     """Workspace bytes for a plan (host only; raises NfsError on a bad desc)."""
     lib = load_library()
-    d, _keep = _desc(n, lags, n_bins, in_dtype, capacity, 1 if window else None)
+    d, _keep = _desc(n, lags, n_bins, in_dtype, capacity, 1 if window else None, spec, accum)
     out = ctypes.c_size_t(0)
     st = lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out))
     if st != NFS_OK:
@@ -112,14 +116,15 @@ def _ptr(t):
 class Plan:
     """A structure-function plan on one GPU.
 
-    Plan(n, lags, n_bins, in_dtype="u16"|"f32", capacity=N, window=None)
+    Plan(n, lags, n_bins, in_dtype="u16"|"f32", capacity=N, window=None,
+         spec="f32"|"bf16"|"f16", accum="plain"|"kahan")
     .push(frames)            frames: [count][n][n] uint16/float32 on the device
     .structure_function()    -> (D float64 [L][n_bins], counts int64 [n_bins],
                                  pairs int64 [L], status int) on the device
     """
 
     def __init__(self, n, lags, n_bins, in_dtype="u16", capacity=0, window=None,
-                 device=None, stream=None):
+                 device=None, stream=None, spec="f32", accum="plain"):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the structure-function library needs one")
@@ -137,7 +142,8 @@ class Plan:
             self.window = w
             wptr = w.data_ptr()
         self.stream = stream or torch.cuda.current_stream(self.device)
-        d, self._lags_keep = _desc(self.n, self.lags, self.n_bins, in_dtype, capacity, wptr)
+        d, self._lags_keep = _desc(self.n, self.lags, self.n_bins, in_dtype, capacity, wptr,
+                                   spec, accum)
         size = ctypes.c_size_t(0)
         st = self.lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(size))
         self._check(st, None)

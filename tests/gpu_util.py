@@ -16,7 +16,8 @@ def require_gpu():
         raise RuntimeError("GPU test run without a visible GPU")
 
 
-def run_plan(frames, lags, n_bins, in_dtype, capacity=None, window=None, chunk=None):
+def run_plan(frames, lags, n_bins, in_dtype, capacity=None, window=None, chunk=None,
+             spec="f32", accum="plain"):
     """Push `frames` (torch or numpy [N][n][n]) through a plan; return numpy results."""
     import paper_1209_3362_amd as nfs
     require_gpu()
@@ -24,7 +25,8 @@ def run_plan(frames, lags, n_bins, in_dtype, capacity=None, window=None, chunk=N
     t = t.to(torch.uint16 if in_dtype == "u16" else torch.float32).to("cuda").contiguous()
     N, n = t.shape[0], t.shape[-1]
     cap = capacity if capacity is not None else max(N, max(lags) + 1)
-    plan = nfs.Plan(n, lags, n_bins, in_dtype=in_dtype, capacity=cap, window=window)
+    plan = nfs.Plan(n, lags, n_bins, in_dtype=in_dtype, capacity=cap, window=window,
+                    spec=spec, accum=accum)
     if chunk:
         for i in range(0, N, chunk):
             plan.push(t[i:i + chunk])

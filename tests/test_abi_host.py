@@ -71,21 +71,33 @@ def test_descriptor_validation():
     assert code(capacity=2**31) == "NFS_E_CAPACITY"
 
 
-def test_unsupported_options_are_rejected():
+def test_storage_and_accumulation_options():
     lib = nfs.load_library()
     arr = (ctypes.c_int32 * 1)(1)
-    for field in ("spec_dtype", "accum"):
-        d = NfsDesc(n=64, in_dtype=1, spec_dtype=0, accum=0, n_lags=1, lags=arr, n_bins=8,
-                    capacity=8, window=None)
-        setattr(d, field, 1)
-        out = ctypes.c_size_t(0)
-        assert lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out)) == 10
+    for field, ok, bad in (("spec_dtype", (0, 1, 2), (3, -1)), ("accum", (0, 1), (2, -1))):
+        for value in ok + bad:
+            d = NfsDesc(n=64, in_dtype=1, spec_dtype=0, accum=0, n_lags=1, lags=arr, n_bins=8,
+                        capacity=8, window=None)
+            setattr(d, field, value)
+            out = ctypes.c_size_t(0)
+            want = 0 if value in ok else 10
+            assert lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out)) == want
     d = NfsDesc(n=64, in_dtype=5, spec_dtype=0, accum=0, n_lags=1, lags=arr, n_bins=8,
                 capacity=8, window=None)
     out = ctypes.c_size_t(0)
     assert lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out)) == 1
     assert lib.nfs_plan_workspace_size(None, ctypes.byref(out)) == 1
     assert lib.nfs_plan_workspace_size(ctypes.byref(d), None) == 1
+
+
+def test_16bit_spectra_halve_the_ring():
+    modes = 412246
+    stride = (modes + 63) // 64 * 64
+    for spec in ("bf16", "f16"):
+        a = size(n=1024, lags=C2_LAGS, n_bins=512, in_dtype="u16", capacity=1000, spec=spec)
+        b = size(n=1024, lags=C2_LAGS, n_bins=512, in_dtype="u16", capacity=1001, spec=spec)
+        assert b - a in (stride * 4 - 256, stride * 4, stride * 4 + 256)
+        assert 1.6e9 < a < 1.9e9
 
 
 def test_workspace_grows_with_capacity_by_one_spectrum_each():
