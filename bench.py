@@ -1,13 +1,15 @@
 """Throughput of the structure-function path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--workload c2|c3] [--spec f32|bf16|f16] [--accum plain|kahan]
 
-Workload: 1000 uint16 frames of 1024x1024 (12-bit camera model, Poisson
-noise), 50 log-spaced lags 1..500, 512 |q| rings. The frames are drawn on
-the GPU and are resident in HBM before timing. One step is the whole path
-on that stack: reset the sums, push the 1000 frames (normalise + 2D
-transform + store), accumulate the lag pairs, bin into D(q, tau). Prints one
-JSON line.
+Default workload (c2): 1000 uint16 frames of 1024x1024 (12-bit camera model,
+Poisson noise), 50 log-spaced lags 1..500, 512 |q| rings, FP32 spectra and
+plain FP32 sums. c3 is the precision workload: 4000 frames of the same model
+with every lag 1..400. The frames are drawn on the GPU and are resident in
+HBM before timing. One step is the whole path on that stack: reset the sums,
+push the frames (normalise + 2D transform + store), accumulate the lag pairs,
+bin into D(q, tau). Prints one JSON line.
 """
 import argparse
 import json
@@ -26,6 +28,12 @@ HBM_PEAK_GBPS = 8000.0
 VALU_LANE_OPS = 256 * 64 * 2.4e9
 FP32_FMA_PEAK_TFLOPS = VALU_LANE_OPS * 2 / 1e12  # 78.6
 
+
+METRIC_C3 = "frame-pairs/sec for D(q,tau), 1024^2 x 4000 frames, lags 1..400, 1 GPU"
+WORKLOADS = {
+    "c2": "1000 uint16 frames 1024x1024, 50 log-spaced lags 1..500, 512 |q| rings",
+    "c3": "4000 uint16 frames 1024x1024, lags 1..400, 512 |q| rings",
+}
 
 PAIR_COUNTERS = os.path.join(ROOT, "profiles", "pair_kernel_1000x1024_counters.md")
 PAIR_SOURCES = ["paper_1209_3362_amd/csrc/pairs.hip", "paper_1209_3362_amd/csrc/nfs_host.hpp",
@@ -69,6 +77,11 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer 5 times (known bytes), to scale "
                          "memory counters of the same profiler run")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--spec", default="f32", choices=["f32", "bf16", "f16"],
+                    help="storage type of the resident spectra")
+    ap.add_argument("--accum", default="plain", choices=["plain", "kahan"],
+                    help="per-mode pair accumulation")
     ap.add_argument("--frames-cache", default=None,
                     help="load the stack from this .npy if it exists, else draw it and "
                          "save it there (lets profiler runs skip the generator)")
@@ -127,7 +140,7 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    cfg = gen.config("c2")
+    cfg = gen.config(args.workload)
     n, N, lags, nb = cfg["n"], cfg["N"], cfg["lags"], cfg["n_bins"]
     frames = None
     if args.frames_cache and os.path.exists(args.frames_cache):
@@ -141,7 +154,8 @@ def main():
             np.save(args.frames_cache, frames.view(torch.int16).cpu().numpy().view(np.uint16))
     torch.cuda.synchronize()
 
-    plan = nfs.Plan(n, lags, nb, in_dtype="u16", capacity=N, device=dev)
+    plan = nfs.Plan(n, lags, nb, in_dtype="u16", capacity=N, device=dev, spec=args.spec,
+                    accum=args.accum)
     stream = plan.stream
     out = plan.empty_outputs()
     M = plan.modes
@@ -186,16 +200,16 @@ def main():
     # (half disc, the modes any ring uses) written once and read once, per-lag
     # sums written and read once.
     bytes_frames = N * n * n * 2
-    bytes_spec = N * M * 8
+    bytes_spec = N * M * (8 if args.spec == "f32" else 4)
     bytes_sums = len(lags) * M * 4
     alg_bytes = bytes_frames + 2 * bytes_spec + 2 * bytes_sums
     pair_k = pairs * M
     # Pair kernel: per pair and mode 2 subtractions + 2 FMAs = 6 FLOP
-    # (4 VALU lane-instructions).
+    # (4 VALU lane-instructions; the Kahan form adds a few per chunk).
     pair_tflops = 6.0 * pair_k / (ms_pair * 1e-3) / 1e12
 
     rec = {
-        "metric": METRIC,
+        "metric": METRIC if args.workload == "c2" else METRIC_C3,
         "value": pairs / (ms_step * 1e-3),
         "unit": "frame-pairs/s",
         "n_gpus": 1,
@@ -207,10 +221,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "1000 uint16 frames 1024x1024, 50 log-spaced lags 1..500, "
-                               "512 |q| rings, seed %d" % args.seed,
+        "config": {"workload": WORKLOADS[args.workload] + ", seed %d" % args.seed,
                    "frames": N, "n": n, "lags": len(lags), "n_bins": nb,
-                   "frame_pairs": pairs, "stored_modes": M, "parallelism": "single GPU"},
+                   "frame_pairs": pairs, "stored_modes": M, "spectra": args.spec,
+                   "accumulation": args.accum, "parallelism": "single GPU"},
         "hbm_gbps_algorithmic": alg_bytes / (ms_step * 1e-3) / 1e9,
         "stage_ms": {"normalise_fft_store": ms_fft, "lag_pairs": ms_pair, "bin": ms_bin},
         "status": st,
@@ -221,11 +235,12 @@ def main():
             "peak": FP32_FMA_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": pair_tflops / FP32_FMA_PEAK_TFLOPS,
-            "traffic": pair_traffic(),
+            "traffic": pair_traffic() if (args.workload, args.spec, args.accum) ==
+                       ("c2", "f32", "plain") else None,
             "valu_issue_frac": 4.0 * pair_k / (ms_pair * 1e-3) / VALU_LANE_OPS,
         },
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "c2":
         rec["cpu_baseline"] = cpu_baseline(frames, cfg, args.cpu_frames)
     plan.close()
     print(json.dumps(rec))

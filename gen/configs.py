@@ -19,6 +19,11 @@ CONFIGS = {
     "c2": dict(name="c2", n=1024, N=1000, dtype="u16", peak=3000.0, eps=0.005,
                gamma_a=0.002, gamma_b=0.5, noise="poisson", noise_sigma=0.0,
                lags=log_spaced_lags(500, 50), n_bins=512),
+    # The precision workload: 4000 frames of the same uint16 model, every lag
+    # from 1 to 400, 512 |q| bins.
+    "c3": dict(name="c3", n=1024, N=4000, dtype="u16", peak=3000.0, eps=0.005,
+               gamma_a=0.002, gamma_b=0.5, noise="poisson", noise_sigma=0.0,
+               lags=list(range(1, 401)), n_bins=512),
     # 256 float frames of 512x512, power-of-two lags up to 64.
     "c5": dict(name="c5", n=512, N=256, dtype="f32", peak=1000.0, eps=0.01,
                gamma_a=0.05, gamma_b=2.0, noise="gauss", noise_sigma=2.0,
