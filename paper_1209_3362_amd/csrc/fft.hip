@@ -13,9 +13,10 @@
 // in double on the host and rounded once to float, kept in LDS with one
 // pad entry per 8 (fewer bank conflicts for strided reads).
 //
-// The intermediate between the passes is [frame][n/4 tiles][n rows][2]:
-// tiles of two columns, so a row pass wave writes 64-byte runs and a column
-// pass wave reads 128-byte runs.
+// The intermediate between the passes is [frame][tiles][n rows][TWD]: tiles
+// of the columns one column-pass workgroup transforms (8 up to n = 1024; at
+// least 2), so a row pass wave writes runs of 4 rows x TWD columns and a
+// column pass wave reads 8 rows x 8 columns contiguously.
 #include "nfs_device.hpp"
 #include "nfs_kernels.hpp"
 
@@ -53,6 +54,24 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <int N>
+struct ColCfg {
+  static constexpr int P1 = 1 << (ilog2(N) / 2);     // N = P1 * P2, P2 in {P1, 2 P1}
+  static constexpr int P2 = N / P1;
+  static constexpr int Q = P2 / P1;
+  static constexpr int CP = pad_2mod16(P2 * (P1 + 1));
+  static constexpr int CW = fit_cols(CP, tw_len(N) * 8);  // columns per workgroup
+  static constexpr int THREADS = CW * P1;
+  static constexpr int GROUPS = (N / 2) / CW;        // column groups per frame
+  // The intermediate is cut into tiles of TWD = max(CW, 2) columns (whole
+  // groups of this pass, or two one-column groups).
+  static constexpr int TWD = CW > 2 ? CW : 2;
+  static constexpr int TILES = (N / 2) / TWD;
+  // Two workgroups per CU while the per-thread store offsets fit the
+  // register budget of two waves per SIMD.
+  static constexpr int MINW = Q * P1 <= 32 ? 2 : 1;
+};
+
+template <int N>
 struct RowCfg {
   static constexpr int H = N / 2;                    // complex points per row
   static constexpr int P1 = 1 << (ilog2(H) / 2);     // H = P1 * P2, P2 in {P1, 2 P1}
@@ -63,23 +82,10 @@ struct RowCfg {
   static constexpr int R = R0 < N ? R0 : N;          // rows per workgroup
   static constexpr int THREADS = R * P1;
   static constexpr int RB = N / R;                   // row blocks per frame
-  static constexpr int TILES = H / 2;                // 2-column tiles of the intermediate
+  // The intermediate is cut into the column pass's tiles.
+  static constexpr int TWD = ColCfg<N>::TWD;
+  static constexpr int TILES = ColCfg<N>::TILES;
   static_assert(64 % P1 == 0, "a row's threads must sit in one wave");
-};
-
-template <int N>
-struct ColCfg {
-  static constexpr int P1 = 1 << (ilog2(N) / 2);     // N = P1 * P2, P2 in {P1, 2 P1}
-  static constexpr int P2 = N / P1;
-  static constexpr int Q = P2 / P1;
-  static constexpr int CP = pad_2mod16(P2 * (P1 + 1));
-  static constexpr int CW = fit_cols(CP, tw_len(N) * 8);  // columns per workgroup
-  static constexpr int THREADS = CW * P1;
-  static constexpr int GROUPS = (N / 2) / CW;        // column groups per frame
-  static constexpr int TILES = N / 4;
-  // Two workgroups per CU while the per-thread store offsets fit the
-  // register budget of two waves per SIMD.
-  static constexpr int MINW = Q * P1 <= 32 ? 2 : 1;
 };
 
 // Frames one workgroup of a pass loops over: enough workgroups to give
@@ -134,7 +140,7 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN, ABS>(
   using Raw = typename RawPair<T>::type;
   constexpr bool U16 = std::is_same<T, uint16_t>::value;
   constexpr int H = C::H, P1 = C::P1, P2 = C::P2, Q = C::Q, R = C::R, RB = C::RB;
-  constexpr int PITCH = C::PITCH, THREADS = C::THREADS, TILES = C::TILES;
+  constexpr int PITCH = C::PITCH, THREADS = C::THREADS, TILES = C::TILES, TWD = C::TWD;
   __shared__ float2 lds[R * PITCH];
   __shared__ float2 twl[tw_len(N)];
 
@@ -272,8 +278,11 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN, ABS>(
     wave_lds_sync();
 
     // Real-input split of this thread's outputs k = j1 + P1 i, stored into
-    // 2-column tiles of the intermediate.
-    float2* dst = inter + ((int64_t(f) * TILES + (j1 >> 1)) * N + y) * 2 + (j1 & 1);
+    // the intermediate: column k % TWD of row y of tile k / TWD.
+    float2* frame_out = inter + int64_t(f) * TILES * N * TWD;
+    // When TWD divides P1, output i of this thread is a fixed stride from
+    // output 0 (one base pointer, compile-time offsets).
+    float2* out0 = frame_out + (int64_t(j1 / TWD) * N + y) * TWD + (j1 % TWD);
 #pragma unroll
     for (int i = 0; i < P2; ++i) {
       const int k = j1 + P1 * i;
@@ -282,7 +291,11 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN, ABS>(
       const float2 e = make_float2(zk.x + zm.x, zk.y - zm.y);   // Z[k] + conj Z[H-k]
       const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);   // Z[k] - conj Z[H-k]
       const float2 wd = cmul(d, twl[tw_skew(k)]);
-      dst[int64_t(i) * (P1 / 2) * N * 2] = make_float2(0.5f * (e.x + wd.y), 0.5f * (e.y - wd.x));
+      const float2 X = make_float2(0.5f * (e.x + wd.y), 0.5f * (e.y - wd.x));
+      if constexpr (P1 % TWD == 0)
+        out0[int64_t(i) * (P1 / TWD) * N * TWD] = X;
+      else
+        frame_out[(int64_t(k / TWD) * N + y) * TWD + (k % TWD)] = X;
     }
     wave_lds_sync();  // the row's LDS is rewritten by the next frame
   }
@@ -343,7 +356,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
   constexpr uint32_t MODE_BYTES = SPEC == kSpecF32 ? 8u : 4u;
   using C = ColCfg<N>;
   constexpr int P1 = C::P1, P2 = C::P2, Q = C::Q, CP = C::CP, CW = C::CW;
-  constexpr int THREADS = C::THREADS, GROUPS = C::GROUPS, TILES = C::TILES;
+  constexpr int THREADS = C::THREADS, GROUPS = C::GROUPS, TILES = C::TILES, TWD = C::TWD;
   constexpr int WW = THREADS < 64 ? THREADS : 64;  // lanes of a (possibly partial) wave
   constexpr int NWAVES = (THREADS + 63) / 64;
   __shared__ float2 lds[CW * CP];
@@ -387,9 +400,10 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
   }
 
   auto load_cols = [&](float2 (&v)[P2], int f) {
-    const float2* src = inter + (int64_t(f) * TILES + (kx >> 1)) * N * 2 + (kx & 1);
+    // Column kx is column kx % TWD of tile kx / TWD of the intermediate.
+    const float2* src = inter + (int64_t(f) * TILES + kx / TWD) * N * TWD + kx % TWD;
 #pragma unroll
-    for (int j2 = 0; j2 < P2; ++j2) v[j2] = src[(j1 + P1 * j2) * 2];
+    for (int j2 = 0; j2 < P2; ++j2) v[j2] = src[(j1 + P1 * j2) * TWD];
   };
   float2 v[P2];
   if (CACHE && f_begin < f_end) load_cols(v, f_begin);

@@ -13,7 +13,8 @@ namespace nfs {
 // transformed. frames: [nframes][n][n] of u16 (in_dtype 0) or f32 (1);
 // ref: [n][n] of the same type subtracted from every frame first, or null;
 // window: [n][n] multiplied in after the subtraction, or null. Writes inter
-// [nframes][n/4][n][2] complex (2-column tiles), rowsum [nframes][n] and,
+// [nframes][tiles][n][w] complex (tiles of the w columns a column-pass
+// workgroup transforms), rowsum [nframes][n] and,
 // when rowabs is not null, rowabs [nframes][n]: the rows' sums of |what was
 // transformed|.
 hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* ref,
