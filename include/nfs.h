@@ -106,6 +106,10 @@ typedef struct {
   const float* window;  /* device [n][n] per-pixel weight multiplied into
                            every frame before normalisation, or NULL;
                            borrowed: must stay valid while the plan is used   */
+  int32_t host_staging; /* 0, or 1 to accept frames from host memory with
+                           nfs_push_host_frames: the workspace then also holds
+                           two device staging buffers of one transform batch
+                           each, and the plan owns a second (copy) stream    */
 } nfs_desc;
 
 /* Bytes of device workspace nfs_plan needs for `desc`. Host only; enqueues
@@ -130,6 +134,22 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes,
  * later pair still needs. Frame indices continue across calls. count == 0 is
  * a no-op. */
 nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count);
+
+/* Streaming ingest: append `count` frames that are in host memory (array
+ * [count][n][n] of the plan's pixel type), for frames that arrive from an
+ * acquisition rather than from device memory. The paper processes images
+ * as they are acquired and names the host-to-device transfer as the
+ * limiting cost (processing and results sections); here each transform
+ * batch is copied on the plan's copy stream into one of two staging
+ * buffers while the plan's stream transforms the previous batch, so the
+ * uploads overlap the transforms and the pair sums. The result is the
+ * same as nfs_push_frames on a device copy of the frames, bit for bit.
+ * `frames` should be pinned (hipHostMalloc, or a pinned torch tensor) for
+ * the copies to run asynchronously; pageable memory is accepted and copied
+ * synchronously by the runtime. Borrowed until the plan's stream passes the
+ * enqueued work. Needs a plan created with host_staging = 1, else
+ * NFS_E_STATE. count == 0 is a no-op. */
+nfs_status nfs_push_host_frames(nfs_handle h, const void* frames, int64_t count);
 
 /* Accumulate the pair sums of every frame pushed so far (enqueued). Needed
  * only to split the work, e.g. to overlap it with acquisition or to time it:

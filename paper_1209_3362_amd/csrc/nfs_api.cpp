@@ -46,7 +46,27 @@ struct nfs_plan_s {
   int32_t* lags = nullptr;
   int64_t t_pushed = 0;  // frames pushed
   int64_t t_done = 0;    // frames whose pairs (as the later frame) are summed
+  // Host pushes (host_staging): two device staging buffers of one batch;
+  // copies run on `copy`, transforms on `stream`. copied[j] marks batch
+  // data in buffer j, freed[j] the end of the transform that read it.
+  char* stage[2] = {nullptr, nullptr};
+  hipStream_t copy = nullptr;
+  hipEvent_t copied[2] = {nullptr, nullptr};
+  hipEvent_t freed[2] = {nullptr, nullptr};
+  bool freed_recorded[2] = {false, false};
+  int next_stage = 0;
   std::string err;
+
+  ~nfs_plan_s() {
+    if (copy) {
+      (void)hipStreamSynchronize(copy);
+      (void)hipStreamDestroy(copy);
+    }
+    for (int j = 0; j < 2; ++j) {
+      if (copied[j]) (void)hipEventDestroy(copied[j]);
+      if (freed[j]) (void)hipEventDestroy(freed[j]);
+    }
+  }
 };
 
 namespace {
@@ -95,6 +115,58 @@ nfs_status clear_sums(nfs_plan_s* h) {
   if (e != hipSuccess) return hip_fail(h, e, "fill kernel launch");
   h->t_pushed = 0;
   h->t_done = 0;
+  return NFS_OK;
+}
+
+// Frames of the next transform batch out of `left` still to push: at most
+// one batch, and no more than the ring can take beyond the largest lag.
+int64_t next_batch(const nfs_plan_s* h, int64_t left) {
+  const int64_t room = h->L.capacity - h->L.max_lag;  // >= 1 by construction
+  int64_t b = left < h->L.batch ? left : h->L.batch;
+  return b < room ? b : room;
+}
+
+// Sum the pending pairs if pushing `b` more frames would overwrite a
+// spectrum one of them needs: frames [t_pushed, t_pushed + b) evict frames
+// up to t_pushed + b - 1 - capacity, and pending pairs need the frames from
+// max(0, t_done - max_lag) on.
+nfs_status make_room(nfs_plan_s* h, int64_t b) {
+  const nfs::Layout& L = h->L;
+  const int64_t needed = h->t_done - L.max_lag > 0 ? h->t_done - L.max_lag : 0;
+  if (h->t_pushed + b - L.capacity > needed) return flush_pairs(h);
+  return NFS_OK;
+}
+
+// Normalise, transform and store `b` frames (device memory, b <= the batch
+// size) as frames [t_pushed, t_pushed + b); make_room must precede it.
+nfs_status transform_batch(nfs_plan_s* h, const char* src, int64_t b) {
+  const nfs::Layout& L = h->L;
+  hipError_t e = hipSuccess;
+  if (h->t_pushed == 0) {
+    // The first frame of the sequence becomes the reference subtracted
+    // from every frame before its transform; differences of transforms
+    // are unchanged, but the stored values no longer carry the static
+    // image, whose low-q coefficients would swamp FP32.
+    e = hipMemcpyAsync(h->ref, src, L.frame_bytes, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "reference copy");
+    e = nfs::launch_row_pass(L.n, L.in_dtype, h->ref, nullptr, h->window, 1, h->inter,
+                             h->rowsum, nullptr, h->tw, h->stream);
+    if (e == hipSuccess)
+      e = nfs::launch_col_pass(L.n, true, NFS_SPEC_F32, h->inter, h->rowsum, nullptr, 1, 0,
+                               L.capacity, L.mode_stride, L.modes, h->width, h->offset, h->tw,
+                               h->ring, h->refspec, h->refscal, h->fscale, h->status,
+                               h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "reference transform launch");
+  }
+  e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->ref, h->window, int(b), h->inter,
+                           h->rowsum, h->rowabs, h->tw, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
+  e = nfs::launch_col_pass(L.n, false, L.spec_dtype, h->inter, h->rowsum, h->rowabs, int(b),
+                           h->t_pushed, L.capacity, L.mode_stride, L.modes, h->width,
+                           h->offset, h->tw, h->ring, h->refspec, h->refscal, h->fscale,
+                           h->status, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
+  h->t_pushed += b;
   return NFS_OK;
 }
 
@@ -169,6 +241,10 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->bin_seg0 = h->seg_row0 + nseg;
   h->part = reinterpret_cast<double*>(h->ws + L.off_part);
   h->part_cnt = reinterpret_cast<long long*>(h->ws + L.off_part_cnt);
+  if (L.host_staging) {
+    h->stage[0] = h->ws + L.off_stage;
+    h->stage[1] = h->stage[0] + size_t(L.batch) * L.frame_bytes;
+  }
 
   const std::vector<float> tw = nfs::twiddle_table(L.n);
   hipError_t e = hipMemcpyAsync(h->tw, tw.data(), tw.size() * sizeof(float),
@@ -196,6 +272,14 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   if (e == hipSuccess)
     e = nfs::launch_fill_u32(h->refspec, size_t(L.mode_stride) * 2, 0u, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && L.host_staging) {
+    // Default priority, like every stream of the library.
+    e = hipStreamCreateWithFlags(&h->copy, hipStreamNonBlocking);
+    for (int j = 0; j < 2 && e == hipSuccess; ++j) {
+      e = hipEventCreateWithFlags(&h->copied[j], hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&h->freed[j], hipEventDisableTiming);
+    }
+  }
   if (e != hipSuccess) {
     delete h;
     return NFS_E_HIP;
@@ -218,50 +302,50 @@ nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count) {
   if (count < 0) return fail(h, NFS_E_ARG, "count must be >= 0");
   if (count == 0) return NFS_OK;
   if (!frames) return fail(h, NFS_E_ARG, "frames is NULL");
-  const nfs::Layout& L = h->L;
-  const size_t px = L.in_dtype == NFS_IN_U16 ? 2 : 4;
-  const size_t frame_bytes = size_t(L.n) * L.n * px;
-  const int64_t room = L.capacity - L.max_lag;  // >= 1 by construction
   int64_t i = 0;
   while (i < count) {
-    int64_t b = count - i;
-    if (b > L.batch) b = L.batch;
-    if (b > room) b = room;
-    // Pushing frames [t_pushed, t_pushed + b) evicts frames up to
-    // t_pushed + b - 1 - capacity; pending pairs need the frames from
-    // max(0, t_done - max_lag) on.
-    const int64_t needed = h->t_done - L.max_lag > 0 ? h->t_done - L.max_lag : 0;
-    if (h->t_pushed + b - L.capacity > needed) {
-      nfs_status st = flush_pairs(h);
-      if (st != NFS_OK) return st;
-    }
-    const char* src = static_cast<const char*>(frames) + size_t(i) * frame_bytes;
+    const int64_t b = next_batch(h, count - i);
+    nfs_status st = make_room(h, b);
+    if (st == NFS_OK)
+      st = transform_batch(h, static_cast<const char*>(frames) + size_t(i) * h->L.frame_bytes, b);
+    if (st != NFS_OK) return st;
+    i += b;
+  }
+  return NFS_OK;
+}
+
+nfs_status nfs_push_host_frames(nfs_handle h, const void* frames, int64_t count) {
+  if (!is_live(h)) return NFS_E_STATE;
+  if (!h->L.host_staging) return fail(h, NFS_E_STATE, "plan was created without host_staging");
+  if (count < 0) return fail(h, NFS_E_ARG, "count must be >= 0");
+  if (count == 0) return NFS_OK;
+  if (!frames) return fail(h, NFS_E_ARG, "frames is NULL");
+  const size_t fb = h->L.frame_bytes;
+  int64_t i = 0;
+  while (i < count) {
+    const int64_t b = next_batch(h, count - i);
+    const int j = h->next_stage;
+    h->next_stage ^= 1;
+    // Copy stream: wait until the transform that last read buffer j is
+    // done, upload the batch, mark it. Plan stream: sum pending pairs if
+    // needed (overlapping the upload), wait for the upload, transform,
+    // mark buffer j free.
     hipError_t e = hipSuccess;
-    if (h->t_pushed == 0) {
-      // The first frame of the sequence becomes the reference subtracted
-      // from every frame before its transform; differences of transforms
-      // are unchanged, but the stored values no longer carry the static
-      // image, whose low-q coefficients would swamp FP32.
-      e = hipMemcpyAsync(h->ref, src, frame_bytes, hipMemcpyDeviceToDevice, h->stream);
-      if (e != hipSuccess) return hip_fail(h, e, "reference copy");
-      e = nfs::launch_row_pass(L.n, L.in_dtype, h->ref, nullptr, h->window, 1, h->inter,
-                               h->rowsum, nullptr, h->tw, h->stream);
-      if (e == hipSuccess)
-        e = nfs::launch_col_pass(L.n, true, NFS_SPEC_F32, h->inter, h->rowsum, nullptr, 1, 0,
-                                 L.capacity, L.mode_stride, L.modes, h->width, h->offset, h->tw,
-                                 h->ring, h->refspec, h->refscal, h->fscale, h->status,
-                                 h->stream);
-      if (e != hipSuccess) return hip_fail(h, e, "reference transform launch");
-    }
-    e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->ref, h->window, int(b), h->inter,
-                             h->rowsum, h->rowabs, h->tw, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
-    e = nfs::launch_col_pass(L.n, false, L.spec_dtype, h->inter, h->rowsum, h->rowabs, int(b),
-                             h->t_pushed, L.capacity, L.mode_stride, L.modes, h->width,
-                             h->offset, h->tw, h->ring, h->refspec, h->refscal, h->fscale,
-                             h->status, h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
-    h->t_pushed += b;
+    if (h->freed_recorded[j]) e = hipStreamWaitEvent(h->copy, h->freed[j], 0);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->stage[j], static_cast<const char*>(frames) + size_t(i) * fb,
+                         size_t(b) * fb, hipMemcpyHostToDevice, h->copy);
+    if (e == hipSuccess) e = hipEventRecord(h->copied[j], h->copy);
+    if (e != hipSuccess) return hip_fail(h, e, "host frame upload");
+    nfs_status st = make_room(h, b);
+    if (st != NFS_OK) return st;
+    e = hipStreamWaitEvent(h->stream, h->copied[j], 0);
+    if (e != hipSuccess) return hip_fail(h, e, "host frame upload");
+    st = transform_batch(h, h->stage[j], b);
+    if (st != NFS_OK) return st;
+    e = hipEventRecord(h->freed[j], h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "staging event");
+    h->freed_recorded[j] = true;
     i += b;
   }
   return NFS_OK;

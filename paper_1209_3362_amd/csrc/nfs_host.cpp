@@ -49,6 +49,8 @@ nfs_status validate_desc(const nfs_desc* d, std::string* err) {
     return fail(NFS_E_UNSUPPORTED, "spec_dtype must be NFS_SPEC_F32, _BF16 or _F16");
   if (d->accum != NFS_ACC_PLAIN && d->accum != NFS_ACC_KAHAN)
     return fail(NFS_E_UNSUPPORTED, "accum must be NFS_ACC_PLAIN or NFS_ACC_KAHAN");
+  if (d->host_staging != 0 && d->host_staging != 1)
+    return fail(NFS_E_ARG, "host_staging must be 0 or 1");
   if (d->n_lags < 1 || !d->lags) return fail(NFS_E_LAGS, "need at least one lag");
   for (int i = 0; i < d->n_lags; ++i) {
     if (d->lags[i] < 0) return fail(NFS_E_LAGS, "lags must be >= 0");
@@ -135,6 +137,8 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.in_dtype = d->in_dtype;
   o.spec_dtype = d->spec_dtype;
   o.accum = d->accum;
+  o.host_staging = d->host_staging;
+  o.frame_bytes = size_t(d->n) * d->n * (d->in_dtype == NFS_IN_U16 ? 2 : 4);
   o.mode_bytes = d->spec_dtype == NFS_SPEC_F32 ? 8 : 4;
   o.lags.assign(d->lags, d->lags + d->n_lags);
   o.max_lag = o.lags.back();
@@ -206,7 +210,8 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_width = take(size_t(o.n) * 4);
   o.off_offset = take(size_t(o.n) * 4);
   o.off_lags = take(size_t(o.n_lags) * 4);
-  o.off_ref = take(size_t(o.n) * o.n * (o.in_dtype == NFS_IN_U16 ? 2 : 4));
+  o.off_ref = take(o.frame_bytes);
+  o.off_stage = take(o.host_staging ? 2 * size_t(o.batch) * o.frame_bytes : 0);
   o.off_refspec = take(size_t(o.mode_stride) * 8);
   o.off_ring = off;
   // Each ring slot holds one spectrum (8 or 4 bytes per mode, whole

@@ -78,6 +78,8 @@ struct Layout {
   int64_t mode_stride = 0; // M rounded up to 64: ring slot and sum-row pitch
   int64_t capacity = 0;    // ring slots
   int batch = 0;           // frames per transform launch
+  int host_staging = 0;    // two staging buffers of `batch` frames for host pushes
+  size_t frame_bytes = 0;  // bytes of one input frame
   int max_lag = 0;
   std::vector<int32_t> lags;
   std::vector<int32_t> row_width;   // [n] stored modes of transform-order row r
@@ -91,6 +93,7 @@ struct Layout {
   size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_rowabs = 0, off_acc = 0;
   size_t off_status = 0, off_tw = 0, off_width = 0, off_offset = 0;
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
+  size_t off_stage = 0;   // host-push staging: 2 x batch frames (host_staging)
   size_t off_fscale = 0;  // after the ring: kScaleBytes per slot
   size_t off_segs = 0, off_part = 0, off_part_cnt = 0;
   size_t off_lags = 0, total = 0;

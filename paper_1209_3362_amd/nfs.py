@@ -44,6 +44,7 @@ class NfsDesc(ctypes.Structure):
         ("n_bins", ctypes.c_int32),
         ("capacity", ctypes.c_int64),
         ("window", ctypes.c_void_p),
+        ("host_staging", ctypes.c_int32),
     ]
 
 
@@ -69,6 +70,7 @@ def load_library():
         "nfs_plan_workspace_size": (i32, [ctypes.POINTER(NfsDesc), ctypes.POINTER(sz)]),
         "nfs_plan": (i32, [ctypes.POINTER(NfsDesc), P, sz, P, ctypes.POINTER(P)]),
         "nfs_push_frames": (i32, [P, P, i64]),
+        "nfs_push_host_frames": (i32, [P, P, i64]),
         "nfs_accumulate": (i32, [P]),
         "nfs_structure_function": (i32, [P, P, P, P, P]),
         "nfs_reset": (i32, [P]),
@@ -88,20 +90,22 @@ def load_library():
     return lib
 
 
-def _desc(n, lags, n_bins, in_dtype, capacity, window_ptr, spec="f32", accum="plain"):
+def _desc(n, lags, n_bins, in_dtype, capacity, window_ptr, spec="f32", accum="plain",
+          host_staging=False):
     arr = (ctypes.c_int32 * len(lags))(*[int(t) for t in lags])
     d = NfsDesc(n=int(n), in_dtype=IN_DTYPES[in_dtype], spec_dtype=SPEC_DTYPES[spec],
                 accum=ACCUMS[accum],
                 n_lags=len(lags), lags=arr, n_bins=int(n_bins),
-                capacity=int(capacity), window=window_ptr)
+                capacity=int(capacity), window=window_ptr, host_staging=int(host_staging))
     return d, arr
 
 
 def workspace_size(n, lags, n_bins, in_dtype="u16", capacity=0, window=False, spec="f32",
-                   accum="plain"):
+                   accum="plain", host_staging=False):
     """Workspace bytes for a plan (host only; raises NfsError on a bad desc)."""
     lib = load_library()
-    d, _keep = _desc(n, lags, n_bins, in_dtype, capacity, 1 if window else None, spec, accum)
+    d, _keep = _desc(n, lags, n_bins, in_dtype, capacity, 1 if window else None, spec, accum,
+                     host_staging)
     out = ctypes.c_size_t(0)
     st = lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out))
     if st != NFS_OK:
@@ -117,14 +121,15 @@ class Plan:
     """A structure-function plan on one GPU.
 
     Plan(n, lags, n_bins, in_dtype="u16"|"f32", capacity=N, window=None,
-         spec="f32"|"bf16"|"f16", accum="plain"|"kahan")
-    .push(frames)            frames: [count][n][n] uint16/float32 on the device
+         spec="f32"|"bf16"|"f16", accum="plain"|"kahan", host_staging=False)
+    .push(frames)            frames: [count][n][n] uint16/float32 on the device, or in
+                             host memory (pinned for overlap) with host_staging=True
     .structure_function()    -> (D float64 [L][n_bins], counts int64 [n_bins],
                                  pairs int64 [L], status int) on the device
     """
 
     def __init__(self, n, lags, n_bins, in_dtype="u16", capacity=0, window=None,
-                 device=None, stream=None, spec="f32", accum="plain"):
+                 device=None, stream=None, spec="f32", accum="plain", host_staging=False):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the structure-function library needs one")
@@ -142,8 +147,10 @@ class Plan:
             self.window = w
             wptr = w.data_ptr()
         self.stream = stream or torch.cuda.current_stream(self.device)
+        self.host_staging = bool(host_staging)
+        self._borrowed = []  # host frames the copy stream may still read
         d, self._lags_keep = _desc(self.n, self.lags, self.n_bins, in_dtype, capacity, wptr,
-                                   spec, accum)
+                                   spec, accum, self.host_staging)
         size = ctypes.c_size_t(0)
         st = self.lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(size))
         self._check(st, None)
@@ -167,17 +174,34 @@ class Plan:
             raise NfsError(st, msg or self.lib.nfs_status_string(st).decode())
 
     def push(self, frames):
-        """Append frames [count][n][n] (device tensor of the plan's pixel type)."""
-        if frames.device != self.device:
-            raise ValueError(f"frames must be on {self.device}")
+        """Append frames [count][n][n] of the plan's pixel type: a device
+        tensor (nfs_push_frames), or a host tensor on a plan made with
+        host_staging=True (nfs_push_host_frames; pinned memory lets the
+        uploads overlap the transforms)."""
+        host = frames.device.type == "cpu"
+        if not host and frames.device != self.device:
+            raise ValueError(f"frames must be on {self.device} or in host memory")
+        if host and not self.host_staging:
+            raise ValueError("host frames need a plan made with host_staging=True")
         if frames.dtype != self.torch_dtype:
             raise ValueError(f"frames must be {self.torch_dtype}")
         if frames.dim() != 3 or tuple(frames.shape[1:]) != (self.n, self.n):
             raise ValueError("frames must be [count][n][n]")
         frames = frames.contiguous()
-        self._check(self.lib.nfs_push_frames(self.handle, _ptr(frames),
-                                             ctypes.c_int64(frames.shape[0])))
+        if host:
+            self._check(self.lib.nfs_push_host_frames(self.handle, _ptr(frames),
+                                                      ctypes.c_int64(frames.shape[0])))
+            # Borrowed until the plan's stream has passed the uploads.
+            self._borrowed.append(frames)
+        else:
+            self._check(self.lib.nfs_push_frames(self.handle, _ptr(frames),
+                                                 ctypes.c_int64(frames.shape[0])))
         return self
+
+    def synchronize(self):
+        """Wait for the plan's stream; releases borrowed host frames."""
+        self.stream.synchronize()
+        self._borrowed.clear()
 
     def accumulate(self):
         """Sum the pairs of every frame pushed so far (enqueued)."""
@@ -198,7 +222,7 @@ class Plan:
         self._check(self.lib.nfs_structure_function(self.handle, _ptr(D), _ptr(counts),
                                                     _ptr(pairs), _ptr(status)))
         if sync:
-            self.stream.synchronize()
+            self.synchronize()
         return D, counts, pairs, status
 
     def power_spectra(self, sync=True):
@@ -227,7 +251,7 @@ class Plan:
 
     def close(self):
         if getattr(self, "handle", None):
-            self.stream.synchronize()
+            self.synchronize()
             self.lib.nfs_destroy(self.handle)
             self.handle = None
 

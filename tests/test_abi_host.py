@@ -110,10 +110,33 @@ def test_workspace_grows_with_capacity_by_one_spectrum_each():
     assert 3.3e9 < a < 3.6e9
 
 
+def test_host_staging_adds_two_batches_of_frames():
+    """Streaming ingest: the workspace holds two staging buffers of one
+    transform batch (32 frames of 1024^2 at 4 MiB of row intermediate per
+    frame under the 128 MiB batch target; 2 or 4 bytes per pixel)."""
+    for dtype, px in (("u16", 2), ("f32", 4)):
+        a = size(n=1024, lags=C2_LAGS, n_bins=512, in_dtype=dtype, capacity=1000)
+        b = size(n=1024, lags=C2_LAGS, n_bins=512, in_dtype=dtype, capacity=1000,
+                 host_staging=True)
+        assert b - a == 2 * 32 * 1024 * 1024 * px
+    # the batch never exceeds capacity - max lag, nor does the staging
+    a = size(n=64, lags=[1, 5], n_bins=16, capacity=8)
+    b = size(n=64, lags=[1, 5], n_bins=16, capacity=8, host_staging=True)
+    assert b - a == 2 * 3 * 64 * 64 * 4
+    lib = nfs.load_library()
+    arr = (ctypes.c_int32 * 1)(1)
+    out = ctypes.c_size_t(0)
+    for value, want in ((0, 0), (1, 0), (2, 1), (-1, 1)):
+        d = NfsDesc(n=64, in_dtype=1, spec_dtype=0, accum=0, n_lags=1, lags=arr, n_bins=8,
+                    capacity=8, window=None, host_staging=value)
+        assert lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out)) == want
+
+
 def test_calls_on_bad_handles_fail_cleanly():
     lib = nfs.load_library()
     assert lib.nfs_destroy(None) == 7
     assert lib.nfs_push_frames(None, None, 0) == 7
+    assert lib.nfs_push_host_frames(None, None, 0) == 7
     assert lib.nfs_structure_function(None, None, None, None, None) == 7
     assert lib.nfs_reset(None) == 7
     assert lib.nfs_last_error(None) == b"invalid handle"
