@@ -15,8 +15,10 @@ from .dda import (normalise, spectra, pair_power, bin_index, bin_counts,
                   structure_function_bins)
 from .precision import (round_bf16, f16_exponent, round_f16_scaled, stored_spectra,
                         structure_function_stored, structure_function_stored_bins)
+from .backward import structure_function_grad
 
 __all__ = ["normalise", "spectra", "pair_power", "bin_index", "bin_counts",
            "azimuthal_average", "structure_function", "structure_function_bins",
            "round_bf16", "f16_exponent", "round_f16_scaled", "stored_spectra",
-           "structure_function_stored", "structure_function_stored_bins"]
+           "structure_function_stored", "structure_function_stored_bins",
+           "structure_function_grad"]
