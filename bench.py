@@ -1,12 +1,16 @@
 """Throughput of the structure-function path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--workload c2|c3] [--spec f32|bf16|f16] [--accum plain|kahan]
+                    [--workload c2|c3|c5] [--spec f32|bf16|f16] [--accum plain|kahan]
+                    [--ingest device|host] [--capacity C]
 
 Default workload (c2): 1000 uint16 frames of 1024x1024 (12-bit camera model,
 Poisson noise), 50 log-spaced lags 1..500, 512 |q| rings, FP32 spectra and
 plain FP32 sums. c3 is the precision workload: 4000 frames of the same model
-with every lag 1..400. The frames are drawn on the GPU and are resident in
+with every lag 1..400. c5 is the differentiation workload: 256 float32
+frames of 512x512 under a Hann window, lags 1, 2, 4, ..., 64, 256 rings; its
+step also runs the gradient of a loss of D with respect to the frames and
+the window (nfs_backward). The frames are drawn on the GPU and are resident in
 HBM before timing. One step is the whole path on that stack: reset the sums,
 push the frames (normalise + 2D transform + store), accumulate the lag pairs,
 bin into D(q, tau). Prints one JSON line.
@@ -30,9 +34,12 @@ FP32_FMA_PEAK_TFLOPS = VALU_LANE_OPS * 2 / 1e12  # 78.6
 
 
 METRIC_C3 = "frame-pairs/sec for D(q,tau), 1024^2 x 4000 frames, lags 1..400, 1 GPU"
+METRIC_C5 = ("frame-pairs/sec for D(q,tau) and its gradient with respect to frames and window, "
+             "512^2 x 256 frames, 1 GPU")
 WORKLOADS = {
     "c2": "1000 uint16 frames 1024x1024, 50 log-spaced lags 1..500, 512 |q| rings",
     "c3": "4000 uint16 frames 1024x1024, lags 1..400, 512 |q| rings",
+    "c5": "256 float32 frames 512x512, Hann window, lags 1,2,4,...,64, 256 |q| rings",
 }
 
 PAIR_COUNTERS = os.path.join(ROOT, "profiles", "pair_kernel_1000x1024_counters.md")
@@ -77,7 +84,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer 5 times (known bytes), to scale "
                          "memory counters of the same profiler run")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"])
     ap.add_argument("--spec", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage type of the resident spectra")
     ap.add_argument("--accum", default="plain", choices=["plain", "kahan"],
@@ -185,6 +192,73 @@ def host_ingest(args, cfg, frames):
     }))
 
 
+def differentiation(args):
+    """c5: forward (push + D) and backward (nfs_backward: gradients of
+    sum(G * D) for a fixed random G with respect to frames and window)."""
+    import numpy as np
+    import torch
+    import gen
+    import paper_1209_3362_amd as nfs
+    cfg = gen.config("c5")
+    n, N, lags, nb = cfg["n"], cfg["N"], cfg["lags"], cfg["n_bins"]
+    frames = gen.make_stack(cfg, args.seed, device="cuda")
+    w = torch.from_numpy(np.outer(np.hanning(n), np.hanning(n)).astype(np.float32)).cuda()
+    G = torch.from_numpy(np.random.default_rng(args.seed).standard_normal((len(lags), nb))).cuda()
+    plan = nfs.Plan(n, lags, nb, in_dtype="f32", capacity=N, window=w, backward=True,
+                    spec=args.spec, accum=args.accum)
+    stream = plan.stream
+    out = plan.empty_outputs()
+    gf = torch.empty(frames.shape, dtype=torch.float32, device="cuda")
+    gw = torch.empty((n, n), dtype=torch.float32, device="cuda")
+    import ctypes
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        plan.reset()
+        plan.push(frames)
+        plan.structure_function(sync=False, out=out)
+        if ev:
+            ev[1].record(stream)
+        plan._check(plan.lib.nfs_backward(plan.handle, ctypes.c_void_p(G.data_ptr()),
+                                          ctypes.c_void_p(frames.data_ptr()),
+                                          ctypes.c_void_p(gf.data_ptr()),
+                                          ctypes.c_void_p(gw.data_ptr())))
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_fwd = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
+    ms_bwd = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    assert bool(torch.isfinite(gf).all()) and bool(torch.isfinite(gw).all())
+    pairs = frame_pairs(N, lags)
+    M = plan.modes
+    # Backward algorithmic traffic: the resident spectra read once, the
+    # frames read once, the frame gradient written once.
+    bwd_bytes = N * M * (8 if args.spec == "f32" else 4) + 2 * N * n * n * 4
+    plan.close()
+    print(json.dumps({
+        "metric": METRIC_C5, "value": pairs / (ms_step * 1e-3), "unit": "frame-pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["c5"] + ", seed %d" % args.seed, "frames": N, "n": n,
+                   "lags": len(lags), "n_bins": nb, "frame_pairs": pairs, "stored_modes": M,
+                   "spectra": args.spec, "accumulation": args.accum,
+                   "parallelism": "single GPU"},
+        "stage_ms": {"forward": ms_fwd, "backward": ms_bwd},
+        "backward_gbps_algorithmic": bwd_bytes / (ms_bwd * 1e-3) / 1e9,
+    }))
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -201,6 +275,10 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
+    if args.workload == "c5":
+        torch.cuda.set_device(0)
+        differentiation(args)
+        return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     cfg = gen.config(args.workload)

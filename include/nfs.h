@@ -110,6 +110,10 @@ typedef struct {
                            nfs_push_host_frames: the workspace then also holds
                            two device staging buffers of one transform batch
                            each, and the plan owns a second (copy) stream    */
+  int32_t backward;     /* 0, or 1 to reserve what nfs_backward needs: one
+                           batch of k-space gradients, per-row sums, an FP64
+                           window-gradient accumulator and per-mode bin
+                           tables                                            */
 } nfs_desc;
 
 /* Bytes of device workspace nfs_plan needs for `desc`. Host only; enqueues
@@ -181,6 +185,27 @@ nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
  * mode, the division is done in double and rounded once. S is owned by the
  * caller. Enqueued on the plan's stream. */
 nfs_status nfs_power_spectra_2d(nfs_handle h, float* S);
+
+/* Differentiation form: gradients of a scalar loss L of D with respect to
+ * the frames and the window. D of Eq. (1) is a smooth function of the
+ * images and of the per-pixel weight w (desc.window; w = 1 without one), so
+ * the adjoint of every step (the azimuthal average, the pair average, the
+ * Fourier transform and the division by the image mean) gives
+ *   dL_dframes float [N][n][n]: dL/di_t(x) (may be NULL),
+ *   dL_dwindow float [n][n]:    dL/dw(x) = sum_t i_t(x) dL/du_t(x), u = w i
+ *                               (may be NULL),
+ * for the upstream gradient dL_dD, double [n_lags][n_bins] on the device
+ * (entries of delays with no pair and of lag 0 are ignored: D does not
+ * depend on the frames there). N is the number of frames pushed so far;
+ * `frames` must be those frames, device [N][n][n] of the plan's pixel type
+ * (the normalisation and window adjoints need the pixels). The k-space
+ * gradient is formed from the resident spectra, so every pushed frame must
+ * still be in the ring (capacity >= N), else NFS_E_STATE; the plan needs
+ * desc.backward = 1, else NFS_E_STATE. FP32 transforms and differences,
+ * FP64 sums of pixels and of the window gradient. Enqueued on the plan's
+ * stream; the plan's sums are not changed. */
+nfs_status nfs_backward(nfs_handle h, const double* dL_dD, const void* frames,
+                        float* dL_dframes, float* dL_dwindow);
 
 /* Forget all frames and sums (enqueued); the plan can be reused. */
 nfs_status nfs_reset(nfs_handle h);

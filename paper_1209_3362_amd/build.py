@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnfs.so")
 
-HIP_SOURCES = ["fft.hip", "pairs.hip", "bins.hip", "misc.hip"]
+HIP_SOURCES = ["fft.hip", "pairs.hip", "bins.hip", "misc.hip", "backward.hip"]
 CPP_SOURCES = ["nfs_host.cpp", "nfs_api.cpp"]
 ARCH = "gfx950"
 

@@ -1,0 +1,352 @@
+// Differentiation form: gradients of a scalar loss L of D with respect to
+// the frames and the per-pixel window, by the adjoint of every step of the
+// forward path, taken in reverse (Eq. 1 and the processing section define
+// the forward steps; the adjoint of each follows from the chain rule).
+//
+// With g[l][b] = dL/dD(b, tau_l) / (C_b (N - tau_l)), per batch of frames:
+//   grad_spectra_kernel  k-space gradient (dL/dRe + i dL/dIm) of every
+//       stored coefficient: G_t(k) = 2 sum_l g[l][b(k)] *
+//       ([t + tau < N] (a_t - a_{t+tau}) + [t >= tau] (a_t - a_{t-tau})),
+//       from the resident spectra a_t (only their differences enter);
+//   inv_col_kernel       Z(y, k_x) = sum_{k_y} G(k_y, k_x) e^{+2 pi i k_y y/n}
+//       over the stored modes (the adjoint of the column transform);
+//   inv_row_kernel       g'(y, x) = Re sum_{k_x} c_k Z(y, k_x) e^{+2 pi i k_x x/n},
+//       c = 1 at k_x = 0 and 2 above (each half-plane mode stands for k and
+//       -k), i.e. dL/di' for the mean-normalised image i' = u / m; also the
+//       row sums of u = w * i and of g' * u;
+//   frame_scal_kernel    per frame 1/m and mean(g' * i') from the row sums;
+//   finish_kernel        dL/du = (g' - mean(g' * i')) / m (adjoint of the
+//       division by the mean), dL/di = w * dL/du, and the window gradient
+//       sum_t i_t * dL/du_t accumulated in FP64 in frame order.
+// Inverse transforms are forward DFTs of conjugated data: sum_k x_k
+// e^{+2 pi i jk/n} = conj(sum_k conj(x_k) e^{-2 pi i jk/n}).
+#include "fft_common.hpp"
+#include "nfs_device.hpp"
+#include "nfs_kernels.hpp"
+
+namespace nfs {
+using namespace dev;
+
+namespace {
+
+__device__ __forceinline__ float2 conjf2(float2 a) { return make_float2(a.x, -a.y); }
+
+__global__ void grad_table_kernel(int n_lags, int n_bins, const double* __restrict__ dL_dD,
+                                  const int64_t* __restrict__ bin_count,
+                                  const int32_t* __restrict__ lags, int64_t n_frames,
+                                  float* __restrict__ gtab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_lags * n_bins) return;
+  const int l = i / n_bins, b = i % n_bins;
+  const int64_t tau = lags[l];
+  const int64_t np = n_frames - tau;
+  const int64_t C = bin_count[b];
+  // Lag 0 (every difference is 0) and delays with no pair carry nothing.
+  gtab[i] = (tau > 0 && np > 0 && C > 0) ? float(dL_dD[i] / (double(C) * double(np))) : 0.f;
+}
+
+// Stored value of frame t at mode m, as the pair kernel pairs it.
+template <int SPEC>
+__device__ __forceinline__ float2 stored_value(const char* __restrict__ ring,
+                                               const float4* __restrict__ fscale,
+                                               const float2* __restrict__ refspec,
+                                               int64_t capacity, int64_t mode_stride, int64_t t,
+                                               int64_t m) {
+  const int64_t slot = t % capacity;
+  const float4 sc = fscale[slot];
+  float2 a;
+  if constexpr (SPEC == kSpecF32) {
+    a = reinterpret_cast<const float2*>(ring)[slot * mode_stride + m];
+  } else {
+    const uint32_t w = reinterpret_cast<const uint32_t*>(ring)[slot * mode_stride + m];
+    a = SPEC == kSpecBF16 ? unpack_bf16(w) : unpack_f16(w);
+    a = make_float2(a.x * sc.z, a.y * sc.z);
+  }
+  const float2 R = refspec[m];
+  return make_float2(fmaf(sc.y, R.x, a.x), fmaf(sc.y, R.y, a.y));
+}
+
+template <int SPEC>
+__global__ __launch_bounds__(256) void grad_spectra_kernel(
+    const char* __restrict__ ring, const float4* __restrict__ fscale,
+    const float2* __restrict__ refspec, int64_t capacity, int64_t mode_stride, int64_t n_modes,
+    const int32_t* __restrict__ mode_bin, const float* __restrict__ gtab,
+    const int32_t* __restrict__ lags, int n_lags, int n_bins, int64_t n_frames, int64_t t0,
+    float2* __restrict__ gk) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= n_modes) return;
+  const int64_t t = t0 + blockIdx.y;
+  const int b = mode_bin[m];
+  const float2 at = stored_value<SPEC>(ring, fscale, refspec, capacity, mode_stride, t, m);
+  float gx = 0.f, gy = 0.f;
+  for (int l = 0; l < n_lags; ++l) {
+    const float c = gtab[l * n_bins + b];
+    if (c == 0.f) continue;
+    const int64_t tau = lags[l];
+    float dx = 0.f, dy = 0.f;
+    if (t + tau < n_frames) {
+      const float2 o =
+          stored_value<SPEC>(ring, fscale, refspec, capacity, mode_stride, t + tau, m);
+      dx += at.x - o.x;
+      dy += at.y - o.y;
+    }
+    if (t >= tau) {
+      const float2 o =
+          stored_value<SPEC>(ring, fscale, refspec, capacity, mode_stride, t - tau, m);
+      dx += at.x - o.x;
+      dy += at.y - o.y;
+    }
+    gx = fmaf(c, dx, gx);
+    gy = fmaf(c, dy, gy);
+  }
+  gk[int64_t(blockIdx.y) * mode_stride + m] = make_float2(2.f * gx, 2.f * gy);
+}
+
+// One workgroup: CW columns k_x of one frame. Input: the stored-mode
+// gradient of the frame (zero at modes that are not stored); output
+// Z[f][y][k_x], row-major with n/2 columns.
+template <int N>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_col_kernel(
+    const float2* __restrict__ gk, int64_t mode_stride, const int32_t* __restrict__ row_width,
+    const int32_t* __restrict__ row_offset, const float2* __restrict__ tw,
+    float2* __restrict__ z) {
+  using C = ColCfg<N>;
+  constexpr int CW = C::CW, CP = C::CP, THREADS = C::THREADS;
+  __shared__ float2 lds[CW * CP];
+  __shared__ float2 twl[tw_len(N)];
+  const int f = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int c = tid % CW, j1 = tid / CW;
+  const int kx = blockIdx.x * CW + c;
+  for (int i = tid; i < N; i += THREADS) twl[tw_skew(i)] = tw[i];
+  __syncthreads();
+  const float2* src = gk + int64_t(f) * mode_stride;
+  float2* dst = z + int64_t(f) * N * (N / 2);
+  dft_vector<N>(
+      lds + c * CP, twl, j1,
+      [&](int r) {
+        return kx < row_width[r] ? conjf2(src[row_offset[r] + kx]) : make_float2(0.f, 0.f);
+      },
+      [&](int y, float2 X) { dst[int64_t(y) * (N / 2) + kx] = conjf2(X); });
+}
+
+// One workgroup: CW rows y of one frame. Reads Z[f][y][0..n/2), writes
+// g'[f][y][0..n) as floats over the same bytes (a row of n/2 complex values
+// and a row of n floats occupy the same bytes; every load of the row
+// precedes the workgroup barrier inside the transform, every store follows
+// it), and rowsums[f][y] = {sum_x u, sum_x g' u} with u = w * i.
+template <int N, typename T, bool WIN>
+__global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_row_kernel(
+    float2* __restrict__ z, const T* __restrict__ frames, const float* __restrict__ window,
+    const float2* __restrict__ tw, double2* __restrict__ rowsums) {
+  using C = ColCfg<N>;
+  constexpr int CW = C::CW, CP = C::CP, THREADS = C::THREADS, P1 = C::P1;
+  __shared__ float2 lds[CW * CP];
+  __shared__ float2 twl[tw_len(N)];
+  __shared__ double2 red[CW][P1];
+  const int f = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int c = tid % CW, j1 = tid / CW;
+  const int y = blockIdx.x * CW + c;
+  for (int i = tid; i < N; i += THREADS) twl[tw_skew(i)] = tw[i];
+  __syncthreads();
+  const int64_t row = int64_t(f) * N + y;
+  const float2* zr = z + row * (N / 2);
+  float* gr = reinterpret_cast<float*>(z) + row * N;
+  const T* ir = frames + row * N;
+  const float* wr = WIN ? window + int64_t(y) * N : nullptr;
+  double su = 0.0, sgu = 0.0;
+  dft_vector<N>(
+      lds + c * CP, twl, j1,
+      [&](int k) {
+        if (k >= N / 2) return make_float2(0.f, 0.f);
+        const float2 v = zr[k];
+        const float s = k == 0 ? 1.f : 2.f;
+        // conj of c_k Z(y, k); at k_x = 0, Z is real (Hermitian column).
+        return k == 0 ? make_float2(v.x, 0.f) : make_float2(s * v.x, -s * v.y);
+      },
+      [&](int x, float2 X) {
+        const float g = X.x;
+        float u = float(ir[x]);
+        if constexpr (WIN) u *= wr[x];
+        su += double(u);
+        sgu += double(g) * double(u);
+        gr[x] = g;
+      });
+  red[c][j1] = make_double2(su, sgu);
+  __syncthreads();
+  if (j1 == 0) {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int j = 0; j < P1; ++j) {
+      a += red[c][j].x;
+      b += red[c][j].y;
+    }
+    rowsums[row] = make_double2(a, b);
+  }
+}
+
+// Per frame: {1/m, mean(g' * i')} with m = mean(u); a frame with m <= 0
+// (degenerate in the forward pass) gets {0, 0}, so its gradient is 0.
+__global__ __launch_bounds__(256) void frame_scal_kernel(int n, const double2* __restrict__ rowsums,
+                                                         double2* __restrict__ scal) {
+  __shared__ double2 red[256];
+  const int f = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int y = threadIdx.x; y < n; y += 256) {
+    const double2 v = rowsums[int64_t(f) * n + y];
+    a += v.x;
+    b += v.y;
+  }
+  red[threadIdx.x] = make_double2(a, b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double su = 0.0, sgu = 0.0;
+    for (int i = 0; i < 256; ++i) {
+      su += red[i].x;
+      sgu += red[i].y;
+    }
+    const double px = double(n) * double(n);
+    const double m = su / px;
+    const bool ok = m > 0.0 && isfinite(m);
+    // mean(g' * i') = (sum g' u / m) / n^2
+    scal[f] = ok ? make_double2(1.0 / m, sgu / (m * px)) : make_double2(0.0, 0.0);
+  }
+}
+
+template <typename T, bool WIN>
+__global__ __launch_bounds__(256) void finish_kernel(
+    int64_t px, int nframes, const float* __restrict__ gprime, const T* __restrict__ frames,
+    const float* __restrict__ window, const double2* __restrict__ scal,
+    float* __restrict__ dL_dframes, double* __restrict__ gw) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= px) return;
+  const float w = WIN ? window[p] : 1.f;
+  double acc = 0.0;
+  for (int f = 0; f < nframes; ++f) {
+    const double2 s = scal[f];
+    const double du = (double(gprime[int64_t(f) * px + p]) - s.y) * s.x;
+    if (dL_dframes) dL_dframes[int64_t(f) * px + p] = float(double(w) * du);
+    acc += double(frames[int64_t(f) * px + p]) * du;
+  }
+  if (gw) gw[p] += acc;
+}
+
+__global__ void window_out_kernel(int64_t px, const double* __restrict__ gw,
+                                  float* __restrict__ out) {
+  const int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < px) out[p] = float(gw[p]);
+}
+
+template <int N>
+hipError_t inverse_2d(int in_dtype, const float2* gk, int64_t mode_stride,
+                      const int32_t* row_width, const int32_t* row_offset, const float2* tw,
+                      int nframes, float2* z, const void* frames, const float* window,
+                      double2* rowsums, hipStream_t s) {
+  using C = ColCfg<N>;
+  hipLaunchKernelGGL(inv_col_kernel<N>, dim3(unsigned(C::GROUPS), unsigned(nframes)),
+                     dim3(C::THREADS), 0, s, gk, mode_stride, row_width, row_offset, tw, z);
+  const dim3 grid(unsigned(N / C::CW), unsigned(nframes));
+  if (in_dtype == 0) {
+    auto fr = static_cast<const uint16_t*>(frames);
+    if (window)
+      hipLaunchKernelGGL((inv_row_kernel<N, uint16_t, true>), grid, dim3(C::THREADS), 0, s, z,
+                         fr, window, tw, rowsums);
+    else
+      hipLaunchKernelGGL((inv_row_kernel<N, uint16_t, false>), grid, dim3(C::THREADS), 0, s,
+                         z, fr, window, tw, rowsums);
+  } else {
+    auto fr = static_cast<const float*>(frames);
+    if (window)
+      hipLaunchKernelGGL((inv_row_kernel<N, float, true>), grid, dim3(C::THREADS), 0, s, z,
+                         fr, window, tw, rowsums);
+    else
+      hipLaunchKernelGGL((inv_row_kernel<N, float, false>), grid, dim3(C::THREADS), 0, s, z,
+                         fr, window, tw, rowsums);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_grad_table(int n_lags, int n_bins, const double* dL_dD,
+                             const int64_t* bin_count, const int32_t* lags, int64_t n_frames,
+                             float* gtab, hipStream_t s) {
+  const int items = n_lags * n_bins;
+  hipLaunchKernelGGL(grad_table_kernel, dim3(unsigned((items + 255) / 256)), dim3(256), 0, s,
+                     n_lags, n_bins, dL_dD, bin_count, lags, n_frames, gtab);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
+                               const float2* refspec, int64_t capacity, int64_t mode_stride,
+                               int64_t n_modes, const int32_t* mode_bin, const float* gtab,
+                               const int32_t* lags, int n_lags, int n_bins, int64_t n_frames,
+                               int64_t t0, int nframes, float2* gk, hipStream_t s) {
+  const dim3 grid(unsigned((n_modes + 255) / 256), unsigned(nframes));
+  const char* r = static_cast<const char*>(ring);
+#define NFS_GRAD_GO(SPECV)                                                                    \
+  hipLaunchKernelGGL(grad_spectra_kernel<SPECV>, grid, dim3(256), 0, s, r, fscale, refspec,  \
+                     capacity, mode_stride, n_modes, mode_bin, gtab, lags, n_lags, n_bins,   \
+                     n_frames, t0, gk)
+  if (spec == kSpecF32)
+    NFS_GRAD_GO(kSpecF32);
+  else if (spec == kSpecBF16)
+    NFS_GRAD_GO(kSpecBF16);
+  else
+    NFS_GRAD_GO(kSpecF16);
+#undef NFS_GRAD_GO
+  return hipGetLastError();
+}
+
+hipError_t launch_inverse_2d(int n, int in_dtype, const float2* gk, int64_t mode_stride,
+                             const int32_t* row_width, const int32_t* row_offset,
+                             const float2* tw, int nframes, float2* z, const void* frames,
+                             const float* window, double2* rowsums, hipStream_t s) {
+  switch (n) {
+#define NFS_INV_CASE(NV)                                                                       \
+  case NV:                                                                                     \
+    return inverse_2d<NV>(in_dtype, gk, mode_stride, row_width, row_offset, tw, nframes, z,  \
+                          frames, window, rowsums, s);
+    NFS_INV_CASE(16)
+    NFS_INV_CASE(32)
+    NFS_INV_CASE(64)
+    NFS_INV_CASE(128)
+    NFS_INV_CASE(256)
+    NFS_INV_CASE(512)
+    NFS_INV_CASE(1024)
+    NFS_INV_CASE(2048)
+    NFS_INV_CASE(4096)
+#undef NFS_INV_CASE
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_grad_finish(int n, int in_dtype, int nframes, const double2* rowsums,
+                              double2* scal, const float* gprime, const void* frames,
+                              const float* window, float* dL_dframes, double* gw,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(frame_scal_kernel, dim3(unsigned(nframes)), dim3(256), 0, s, n, rowsums,
+                     scal);
+  const int64_t px = int64_t(n) * n;
+  const dim3 grid(unsigned((px + 255) / 256));
+#define NFS_FIN_GO(T, W)                                                                      \
+  hipLaunchKernelGGL((finish_kernel<T, W>), grid, dim3(256), 0, s, px, nframes, gprime,      \
+                     static_cast<const T*>(frames), window, scal, dL_dframes, gw)
+  if (in_dtype == 0) {
+    if (window) NFS_FIN_GO(uint16_t, true); else NFS_FIN_GO(uint16_t, false);
+  } else {
+    if (window) NFS_FIN_GO(float, true); else NFS_FIN_GO(float, false);
+  }
+#undef NFS_FIN_GO
+  return hipGetLastError();
+}
+
+hipError_t launch_window_out(int n, const double* gw, float* out, hipStream_t s) {
+  const int64_t px = int64_t(n) * n;
+  hipLaunchKernelGGL(window_out_kernel, dim3(unsigned((px + 255) / 256)), dim3(256), 0, s, px,
+                     gw, out);
+  return hipGetLastError();
+}
+
+}  // namespace nfs

@@ -17,6 +17,7 @@
 // of the columns one column-pass workgroup transforms (8 up to n = 1024; at
 // least 2), so a row pass wave writes runs of 4 rows x TWD columns and a
 // column pass wave reads 8 rows x 8 columns contiguously.
+#include "fft_common.hpp"
 #include "nfs_device.hpp"
 #include "nfs_kernels.hpp"
 
@@ -24,25 +25,6 @@ namespace nfs {
 using namespace dev;
 
 namespace {
-
-constexpr int kLdsBudget = 80 * 1024;  // per workgroup, so two fit per CU
-
-// Exchange twiddle table in LDS: entry m at m + m/8.
-__host__ __device__ constexpr int tw_skew(int m) { return m + (m >> 3); }
-constexpr int tw_len(int n) { return n + n / 8; }
-
-constexpr int fit_rows(int r, int pitch, int fixed) {
-  while (r > 1 && r * pitch * 8 + fixed > kLdsBudget) r /= 2;
-  return r;
-}
-// LDS column pitch congruent to 2 mod 16 complex values, so 8 columns x 2
-// rows of 8-byte accesses fall in 16 distinct bank pairs.
-constexpr int pad_2mod16(int v) { return v + ((2 - v % 16) + 16) % 16; }
-constexpr int fit_cols(int pitch, int fixed) {
-  int c = 8;
-  while (c > 1 && c * pitch * 8 + fixed > kLdsBudget) c /= 2;
-  return c;
-}
 
 // Orders a wave's LDS writes before later LDS reads of other lanes of the
 // same wave: the exchanges of the row pass never leave a wave, so no
@@ -52,24 +34,6 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-
-template <int N>
-struct ColCfg {
-  static constexpr int P1 = 1 << (ilog2(N) / 2);     // N = P1 * P2, P2 in {P1, 2 P1}
-  static constexpr int P2 = N / P1;
-  static constexpr int Q = P2 / P1;
-  static constexpr int CP = pad_2mod16(P2 * (P1 + 1));
-  static constexpr int CW = fit_cols(CP, tw_len(N) * 8);  // columns per workgroup
-  static constexpr int THREADS = CW * P1;
-  static constexpr int GROUPS = (N / 2) / CW;        // column groups per frame
-  // The intermediate is cut into tiles of TWD = max(CW, 2) columns (whole
-  // groups of this pass, or two one-column groups).
-  static constexpr int TWD = CW > 2 ? CW : 2;
-  static constexpr int TILES = (N / 2) / TWD;
-  // Two workgroups per CU while the per-thread store offsets fit the
-  // register budget of two waves per SIMD.
-  static constexpr int MINW = Q * P1 <= 32 ? 2 : 1;
-};
 
 template <int N>
 struct RowCfg {

@@ -55,6 +55,14 @@ struct nfs_plan_s {
   hipEvent_t freed[2] = {nullptr, nullptr};
   bool freed_recorded[2] = {false, false};
   int next_stage = 0;
+  // nfs_backward buffers (backward)
+  float2* gk = nullptr;
+  double2* brow = nullptr;
+  double2* bscal = nullptr;
+  double* gw = nullptr;
+  float* gtab = nullptr;
+  int32_t* mode_bin = nullptr;
+  int64_t* bin_count = nullptr;
   std::string err;
 
   ~nfs_plan_s() {
@@ -241,6 +249,15 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->bin_seg0 = h->seg_row0 + nseg;
   h->part = reinterpret_cast<double*>(h->ws + L.off_part);
   h->part_cnt = reinterpret_cast<long long*>(h->ws + L.off_part_cnt);
+  if (L.backward) {
+    h->gk = reinterpret_cast<float2*>(h->ws + L.off_gk);
+    h->brow = reinterpret_cast<double2*>(h->ws + L.off_brow);
+    h->bscal = reinterpret_cast<double2*>(h->ws + L.off_bscal);
+    h->gw = reinterpret_cast<double*>(h->ws + L.off_gw);
+    h->gtab = reinterpret_cast<float*>(h->ws + L.off_gtab);
+    h->mode_bin = reinterpret_cast<int32_t*>(h->ws + L.off_mode_bin);
+    h->bin_count = reinterpret_cast<int64_t*>(h->ws + L.off_bin_count);
+  }
   if (L.host_staging) {
     h->stage[0] = h->ws + L.off_stage;
     h->stage[1] = h->stage[0] + size_t(L.batch) * L.frame_bytes;
@@ -266,6 +283,12 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
                        h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->bin_seg0, L.bin_seg0.data(), L.bin_seg0.size() * 4,
+                       hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess && L.backward)
+    e = hipMemcpyAsync(h->mode_bin, L.mode_bin.data(), L.mode_bin.size() * 4,
+                       hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess && L.backward)
+    e = hipMemcpyAsync(h->bin_count, L.bin_count.data(), L.bin_count.size() * 8,
                        hipMemcpyHostToDevice, h->stream);
   // The pair kernel reads the reference transform in whole workgroup tiles
   // of modes, up to mode_stride; entries past the stored modes stay zero.
@@ -380,6 +403,41 @@ nfs_status nfs_power_spectra_2d(nfs_handle h, float* S) {
   hipError_t e = nfs::launch_power_spectra(L.n, L.n_lags, h->acc, h->width, h->offset, h->lags,
                                            h->t_pushed, S, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "power spectra launch");
+  return NFS_OK;
+}
+
+nfs_status nfs_backward(nfs_handle h, const double* dL_dD, const void* frames,
+                        float* dL_dframes, float* dL_dwindow) {
+  if (!is_live(h)) return NFS_E_STATE;
+  const nfs::Layout& L = h->L;
+  if (!L.backward) return fail(h, NFS_E_STATE, "plan was created without backward");
+  if (!dL_dD) return fail(h, NFS_E_ARG, "dL_dD is NULL");
+  if (!frames) return fail(h, NFS_E_ARG, "frames is NULL");
+  const int64_t N = h->t_pushed;
+  if (N < 1) return fail(h, NFS_E_STATE, "no frame pushed");
+  if (N > L.capacity)
+    return fail(h, NFS_E_STATE, "the gradient needs every pushed frame in the ring (capacity >= frames)");
+  const int64_t px = int64_t(L.n) * L.n;
+  hipError_t e = nfs::launch_grad_table(L.n_lags, L.n_bins, dL_dD, h->bin_count, h->lags, N,
+                                        h->gtab, h->stream);
+  if (e == hipSuccess && dL_dwindow) e = nfs::launch_fill_u32(h->gw, size_t(px) * 2, 0u, h->stream);
+  for (int64_t t0 = 0; e == hipSuccess && t0 < N; t0 += L.batch) {
+    const int b = int(N - t0 < L.batch ? N - t0 : L.batch);
+    const char* fr = static_cast<const char*>(frames) + size_t(t0) * L.frame_bytes;
+    e = nfs::launch_grad_spectra(h->ring, L.spec_dtype, h->fscale, h->refspec, L.capacity,
+                                 L.mode_stride, L.modes, h->mode_bin, h->gtab, h->lags,
+                                 L.n_lags, L.n_bins, N, t0, b, h->gk, h->stream);
+    if (e == hipSuccess)
+      e = nfs::launch_inverse_2d(L.n, L.in_dtype, h->gk, L.mode_stride, h->width, h->offset,
+                                 h->tw, b, h->inter, fr, h->window, h->brow, h->stream);
+    if (e == hipSuccess)
+      e = nfs::launch_grad_finish(L.n, L.in_dtype, b, h->brow, h->bscal,
+                                  reinterpret_cast<const float*>(h->inter), fr, h->window,
+                                  dL_dframes ? dL_dframes + size_t(t0) * px : nullptr,
+                                  dL_dwindow ? h->gw : nullptr, h->stream);
+  }
+  if (e == hipSuccess && dL_dwindow) e = nfs::launch_window_out(L.n, h->gw, dL_dwindow, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "backward launch");
   return NFS_OK;
 }
 

@@ -51,6 +51,7 @@ nfs_status validate_desc(const nfs_desc* d, std::string* err) {
     return fail(NFS_E_UNSUPPORTED, "accum must be NFS_ACC_PLAIN or NFS_ACC_KAHAN");
   if (d->host_staging != 0 && d->host_staging != 1)
     return fail(NFS_E_ARG, "host_staging must be 0 or 1");
+  if (d->backward != 0 && d->backward != 1) return fail(NFS_E_ARG, "backward must be 0 or 1");
   if (d->n_lags < 1 || !d->lags) return fail(NFS_E_LAGS, "need at least one lag");
   for (int i = 0; i < d->n_lags; ++i) {
     if (d->lags[i] < 0) return fail(NFS_E_LAGS, "lags must be >= 0");
@@ -138,6 +139,7 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.spec_dtype = d->spec_dtype;
   o.accum = d->accum;
   o.host_staging = d->host_staging;
+  o.backward = d->backward;
   o.frame_bytes = size_t(d->n) * d->n * (d->in_dtype == NFS_IN_U16 ? 2 : 4);
   o.mode_bytes = d->spec_dtype == NFS_SPEC_F32 ? 8 : 4;
   o.lags.assign(d->lags, d->lags + d->n_lags);
@@ -212,6 +214,29 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_lags = take(size_t(o.n_lags) * 4);
   o.off_ref = take(o.frame_bytes);
   o.off_stage = take(o.host_staging ? 2 * size_t(o.batch) * o.frame_bytes : 0);
+  if (o.backward) {
+    o.off_gk = take(size_t(o.batch) * o.mode_stride * 8);
+    o.off_brow = take(size_t(o.batch) * o.n * 16);
+    o.off_bscal = take(size_t(o.batch) * 16);
+    o.off_gw = take(size_t(o.n) * o.n * 8);
+    o.off_gtab = take(size_t(o.n_lags) * o.n_bins * 4);
+    o.off_mode_bin = take(size_t(o.mode_stride) * 4);
+    o.off_bin_count = take(size_t(o.n_bins) * 8);
+    // Bin of every stored mode and C_b, the full-plane modes of each bin:
+    // a half-plane mode with k_x > 0 stands for itself and its mirror.
+    o.mode_bin.assign(size_t(o.mode_stride), 0);
+    o.bin_count.assign(size_t(o.n_bins), 0);
+    const uint64_t nb2 = uint64_t(o.n_bins) * uint64_t(o.n_bins);
+    for (int r = 0; r < o.n; ++r) {
+      const int64_t ky = r < o.h ? r : r - o.n;
+      for (int kx = 0; kx < o.row_width[r]; ++kx) {
+        const uint64_t k2 = uint64_t(ky * ky) + uint64_t(kx) * uint64_t(kx);
+        const int b = int(isqrt_u64(k2 * nb2) / uint64_t(o.h));
+        o.mode_bin[size_t(o.row_offset[r] + kx)] = b;
+        o.bin_count[size_t(b)] += kx == 0 ? 1 : 2;
+      }
+    }
+  }
   o.off_refspec = take(size_t(o.mode_stride) * 8);
   o.off_ring = off;
   // Each ring slot holds one spectrum (8 or 4 bytes per mode, whole

@@ -80,6 +80,7 @@ struct Layout {
   int batch = 0;           // frames per transform launch
   int host_staging = 0;    // two staging buffers of `batch` frames for host pushes
   size_t frame_bytes = 0;  // bytes of one input frame
+  int backward = 0;        // nfs_backward buffers reserved
   int max_lag = 0;
   std::vector<int32_t> lags;
   std::vector<int32_t> row_width;   // [n] stored modes of transform-order row r
@@ -94,6 +95,14 @@ struct Layout {
   size_t off_status = 0, off_tw = 0, off_width = 0, off_offset = 0;
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
   size_t off_stage = 0;   // host-push staging: 2 x batch frames (host_staging)
+  // nfs_backward (backward): k-space gradients of a batch [batch][mode_stride]
+  // complex, per-row sums [batch][n] and per-frame scalars [batch] (two
+  // doubles each), window gradient [n][n] FP64, g table [n_lags][n_bins],
+  // bin of every stored mode [mode_stride], full-plane modes per bin.
+  size_t off_gk = 0, off_brow = 0, off_bscal = 0, off_gw = 0, off_gtab = 0;
+  size_t off_mode_bin = 0, off_bin_count = 0;
+  std::vector<int32_t> mode_bin;   // [mode_stride], 0 past the stored modes
+  std::vector<int64_t> bin_count;  // [n_bins]
   size_t off_fscale = 0;  // after the ring: kScaleBytes per slot
   size_t off_segs = 0, off_part = 0, off_part_cnt = 0;
   size_t off_lags = 0, total = 0;

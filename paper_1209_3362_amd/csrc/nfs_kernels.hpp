@@ -89,4 +89,43 @@ hipError_t launch_power_spectra(int n, int n_lags, const float* acc, const int32
                                 const int32_t* row_offset, const int32_t* lags,
                                 int64_t n_frames, float* out, hipStream_t s);
 
+// Differentiation form (nfs_backward). g table: gtab[l][b] =
+// dL_dD[l][b] / (C_b (N - lag_l)), 0 for lag 0, delays with no pair and
+// empty bins.
+hipError_t launch_grad_table(int n_lags, int n_bins, const double* dL_dD,
+                             const int64_t* bin_count, const int32_t* lags, int64_t n_frames,
+                             float* gtab, hipStream_t s);
+
+// k-space gradient of frames [t0, t0 + nframes) on the stored modes:
+// gk[f][m] = 2 sum_l gtab[l][mode_bin[m]] * ([t + lag < N] (a_t - a_{t+lag})
+// + [t >= lag] (a_t - a_{t-lag})), a_t decoded as by the pair kernel. Every
+// frame of [0, N) must be in the ring.
+hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
+                               const float2* refspec, int64_t capacity, int64_t mode_stride,
+                               int64_t n_modes, const int32_t* mode_bin, const float* gtab,
+                               const int32_t* lags, int n_lags, int n_bins, int64_t n_frames,
+                               int64_t t0, int nframes, float2* gk, hipStream_t s);
+
+// Adjoint of the 2D transform for nframes frames: inverse column transforms
+// of gk (stored modes, [nframes][mode_stride]) into z [nframes][n][n/2]
+// complex, then per row the real inverse transform with the half-plane
+// weights, written over z as g' [nframes][n][n] floats, and rowsums
+// [nframes][n] = {sum_x u, sum_x g' u} with u = window * frame (frames: the
+// batch's [nframes][n][n] pixels of in_dtype; window may be null).
+hipError_t launch_inverse_2d(int n, int in_dtype, const float2* gk, int64_t mode_stride,
+                             const int32_t* row_width, const int32_t* row_offset,
+                             const float2* tw, int nframes, float2* z, const void* frames,
+                             const float* window, double2* rowsums, hipStream_t s);
+
+// Adjoint of the normalisation and window product for nframes frames:
+// scal[f] = {1/m, mean(g' i')}; dL_dframes[f] = w (g' - mean(g' i')) / m
+// (if not null) and gw += sum_f frame_f (g' - mean(g' i')) / m (if not null).
+hipError_t launch_grad_finish(int n, int in_dtype, int nframes, const double2* rowsums,
+                              double2* scal, const float* gprime, const void* frames,
+                              const float* window, float* dL_dframes, double* gw,
+                              hipStream_t s);
+
+// out[p] = float(gw[p]) for the n x n pixels.
+hipError_t launch_window_out(int n, const double* gw, float* out, hipStream_t s);
+
 }  // namespace nfs

@@ -45,6 +45,7 @@ class NfsDesc(ctypes.Structure):
         ("capacity", ctypes.c_int64),
         ("window", ctypes.c_void_p),
         ("host_staging", ctypes.c_int32),
+        ("backward", ctypes.c_int32),
     ]
 
 
@@ -81,6 +82,7 @@ def load_library():
         "nfs_bin_map": (i32, [P, P]),
         "nfs_copy_spectrum": (i32, [P, i64, P]),
         "nfs_power_spectra_2d": (i32, [P, P]),
+        "nfs_backward": (i32, [P, P, P, P, P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -91,21 +93,22 @@ def load_library():
 
 
 def _desc(n, lags, n_bins, in_dtype, capacity, window_ptr, spec="f32", accum="plain",
-          host_staging=False):
+          host_staging=False, backward=False):
     arr = (ctypes.c_int32 * len(lags))(*[int(t) for t in lags])
     d = NfsDesc(n=int(n), in_dtype=IN_DTYPES[in_dtype], spec_dtype=SPEC_DTYPES[spec],
                 accum=ACCUMS[accum],
                 n_lags=len(lags), lags=arr, n_bins=int(n_bins),
-                capacity=int(capacity), window=window_ptr, host_staging=int(host_staging))
+                capacity=int(capacity), window=window_ptr, host_staging=int(host_staging),
+                backward=int(backward))
     return d, arr
 
 
 def workspace_size(n, lags, n_bins, in_dtype="u16", capacity=0, window=False, spec="f32",
-                   accum="plain", host_staging=False):
+                   accum="plain", host_staging=False, backward=False):
     """Workspace bytes for a plan (host only; raises NfsError on a bad desc)."""
     lib = load_library()
     d, _keep = _desc(n, lags, n_bins, in_dtype, capacity, 1 if window else None, spec, accum,
-                     host_staging)
+                     host_staging, backward)
     out = ctypes.c_size_t(0)
     st = lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out))
     if st != NFS_OK:
@@ -121,15 +124,18 @@ class Plan:
     """A structure-function plan on one GPU.
 
     Plan(n, lags, n_bins, in_dtype="u16"|"f32", capacity=N, window=None,
-         spec="f32"|"bf16"|"f16", accum="plain"|"kahan", host_staging=False)
+         spec="f32"|"bf16"|"f16", accum="plain"|"kahan", host_staging=False,
+         backward=False)
     .push(frames)            frames: [count][n][n] uint16/float32 on the device, or in
                              host memory (pinned for overlap) with host_staging=True
     .structure_function()    -> (D float64 [L][n_bins], counts int64 [n_bins],
                                  pairs int64 [L], status int) on the device
+    .backward(dL_dD, frames) -> (dL/dframes, dL/dwindow) (plans made with backward=True)
     """
 
     def __init__(self, n, lags, n_bins, in_dtype="u16", capacity=0, window=None,
-                 device=None, stream=None, spec="f32", accum="plain", host_staging=False):
+                 device=None, stream=None, spec="f32", accum="plain", host_staging=False,
+                 backward=False):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the structure-function library needs one")
@@ -150,7 +156,7 @@ class Plan:
         self.host_staging = bool(host_staging)
         self._borrowed = []  # host frames the copy stream may still read
         d, self._lags_keep = _desc(self.n, self.lags, self.n_bins, in_dtype, capacity, wptr,
-                                   spec, accum, self.host_staging)
+                                   spec, accum, self.host_staging, backward)
         size = ctypes.c_size_t(0)
         st = self.lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(size))
         self._check(st, None)
@@ -234,6 +240,28 @@ class Plan:
             self.stream.synchronize()
         return out
 
+    def backward(self, dL_dD, frames, frames_grad=True, window_grad=True, sync=True):
+        """nfs_backward: gradients of a loss with upstream gradient dL_dD
+        [L][n_bins] with respect to `frames` (the frames pushed so far, on the
+        device) and the window. Returns (float32 [N][n][n] or None,
+        float32 [n][n] or None)."""
+        g = dL_dD.to(device=self.device, dtype=torch.float64).contiguous()
+        if tuple(g.shape) != (len(self.lags), self.n_bins):
+            raise ValueError("dL_dD must be [n_lags][n_bins]")
+        if frames.device != self.device or frames.dtype != self.torch_dtype:
+            raise ValueError(f"frames must be {self.torch_dtype} on {self.device}")
+        frames = frames.contiguous()
+        gf = torch.empty(frames.shape, dtype=torch.float32, device=self.device) \
+            if frames_grad else None
+        gw = torch.empty((self.n, self.n), dtype=torch.float32, device=self.device) \
+            if window_grad else None
+        self._check(self.lib.nfs_backward(self.handle, _ptr(g), _ptr(frames),
+                                          _ptr(gf) if gf is not None else None,
+                                          _ptr(gw) if gw is not None else None))
+        if sync:
+            self.synchronize()
+        return gf, gw
+
     def bin_map(self):
         out = torch.empty((self.n, self.n // 2), dtype=torch.int32, device=self.device)
         self._check(self.lib.nfs_bin_map(self.handle, _ptr(out)))
@@ -260,3 +288,43 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class _StructureFunction(torch.autograd.Function):
+    """D(q, tau) of a frame stack as a differentiable function of the frames
+    and the window: the forward pushes the stack through a plan, the
+    backward calls nfs_backward on the same plan."""
+
+    @staticmethod
+    def forward(ctx, frames, window, lags, n_bins, spec, accum):
+        in_dtype = "u16" if frames.dtype == torch.uint16 else "f32"
+        N, n = frames.shape[0], frames.shape[-1]
+        plan = Plan(n, lags, n_bins, in_dtype=in_dtype, capacity=max(N, max(lags) + 1),
+                    window=None if window is None else window.detach(), spec=spec,
+                    accum=accum, backward=True, device=frames.device)
+        frames = frames.detach().contiguous()
+        plan.push(frames)
+        D, _, _, st = plan.structure_function()
+        if int(st.item()) != NFS_OK:
+            plan.close()
+            raise NfsError(int(st.item()), "a frame had a non-positive spatial sum")
+        ctx.plan = plan
+        ctx.save_for_backward(frames)
+        return D
+
+    @staticmethod
+    def backward(ctx, dD):
+        (frames,) = ctx.saved_tensors
+        plan = ctx.plan
+        want_f, want_w = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+        gf, gw = plan.backward(dD, frames, frames_grad=want_f, window_grad=want_w)
+        plan.close()
+        ctx.plan = None
+        return gf, gw, None, None, None, None
+
+
+def structure_function(frames, lags, n_bins, window=None, spec="f32", accum="plain"):
+    """D [L][n_bins] (float64) of a device frame stack [N][n][n], differentiable
+    with respect to float32 frames and the window (torch autograd)."""
+    return _StructureFunction.apply(frames, window, [int(t) for t in lags], int(n_bins), spec,
+                                    accum)

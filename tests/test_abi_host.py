@@ -132,11 +132,39 @@ def test_host_staging_adds_two_batches_of_frames():
         assert lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out)) == want
 
 
+def test_backward_reserves_its_buffers():
+    """Differentiation form: one batch of k-space gradients (mode_stride
+    complex each), per-row sums (16 B per row), per-frame scalars, an FP64
+    window gradient, the g table, the mode-bin table and the bin counts, each
+    rounded up to 256 bytes."""
+    def up(v):
+        return (v + 255) // 256 * 256
+    n, lags, nb, cap = 128, [1, 2, 4], 64, 64
+    a = size(n=n, lags=lags, n_bins=nb, capacity=cap)
+    b = size(n=n, lags=lags, n_bins=nb, capacity=cap, backward=True)
+    half = n // 2
+    M = sum(int(((half * half - 1 - ky * ky)) ** 0.5 + 1e-9) + 1
+            for ky in [r if r < half else r - n for r in range(n)] if half * half - 1 - ky * ky >= 0)
+    stride = (M + 63) // 64 * 64
+    batch = min(1024, (128 << 20) // (n * half * 8), cap - max(lags))
+    want = (up(batch * stride * 8) + up(batch * n * 16) + up(batch * 16) + up(n * n * 8)
+            + up(len(lags) * nb * 4) + up(stride * 4) + up(nb * 8))
+    assert b - a == want
+    lib = nfs.load_library()
+    arr = (ctypes.c_int32 * 1)(1)
+    out = ctypes.c_size_t(0)
+    for value, want in ((0, 0), (1, 0), (2, 1), (-1, 1)):
+        d = NfsDesc(n=64, in_dtype=1, spec_dtype=0, accum=0, n_lags=1, lags=arr, n_bins=8,
+                    capacity=8, window=None, backward=value)
+        assert lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out)) == want
+
+
 def test_calls_on_bad_handles_fail_cleanly():
     lib = nfs.load_library()
     assert lib.nfs_destroy(None) == 7
     assert lib.nfs_push_frames(None, None, 0) == 7
     assert lib.nfs_push_host_frames(None, None, 0) == 7
+    assert lib.nfs_backward(None, None, None, None, None) == 7
     assert lib.nfs_structure_function(None, None, None, None, None) == 7
     assert lib.nfs_reset(None) == 7
     assert lib.nfs_last_error(None) == b"invalid handle"

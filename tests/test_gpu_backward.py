@@ -1,0 +1,155 @@
+"""Differentiation form on the GPU (nfs_backward): gradients of a loss of D
+with respect to the frames and the window against the FP64 oracle adjoint
+(oracle/backward.py, itself pinned by central differences and torch
+autograd).
+
+Tolerance: the GPU forms the k-space gradient from FP32 spectra and runs
+FP32 inverse transforms, so each gradient entry carries an error of a few
+FP32 roundings of the largest entries of its frame; the bar is a maximum
+absolute error of 1e-4 of the largest gradient entry (of the frame
+gradient, and of the window gradient)."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _hann(n):
+    return np.outer(np.hanning(n), np.hanning(n))
+
+
+def _check(name, got, want, tol=1e-4):
+    scale = np.abs(want).max()
+    err = np.abs(got - want).max()
+    print(f"{name}: max |err| / max |grad| = {err / scale:.2e}")
+    assert err <= tol * scale, (name, err / scale)
+
+
+def _run(frames, lags, n_bins, G, window, in_dtype="f32", spec="f32", chunk=None):
+    import paper_1209_3362_amd as nfs
+    N, n = frames.shape[0], frames.shape[-1]
+    t = frames.to("cuda")
+    w = None if window is None else torch.from_numpy(window.astype(np.float32)).cuda()
+    plan = nfs.Plan(n, lags, n_bins, in_dtype=in_dtype, capacity=max(N, max(lags) + 1),
+                    window=w, spec=spec, backward=True)
+    if chunk:
+        for i in range(0, N, chunk):
+            plan.push(t[i:i + chunk])
+    else:
+        plan.push(t)
+    gf, gw = plan.backward(torch.from_numpy(G), t)
+    out = gf.cpu().numpy(), gw.cpu().numpy()
+    plan.close()
+    return out
+
+
+def test_backward_matches_oracle_windowed_f32():
+    require_gpu()
+    cfg = gen.config("c1", N=40)
+    lags = [0, 1, 2, 4, 8, 16, 39, 40]
+    say("backward: 40 frames 128x128 f32, Hann window, lags 0..40, 64 bins, seed 41")
+    f = gen.make_stack(cfg, 41)
+    w = _hann(128)
+    G = np.random.default_rng(41).standard_normal((len(lags), 64))
+    want = oracle.structure_function_grad(f.numpy(), lags, 64, G, window=w)
+    gf, gw = _run(f, lags, 64, G, w, chunk=13)
+    _check("frames", gf, want["frames"])
+    _check("window", gw, want["window"])
+
+
+def test_backward_matches_oracle_u16_without_window():
+    require_gpu()
+    cfg = gen.config("c2", n=64, N=50, lags=[1, 3, 7, 20], n_bins=32)
+    say("backward: 50 frames 64x64 u16, no window, lags 1,3,7,20, 32 bins, seed 42")
+    f = gen.make_stack(cfg, 42)
+    G = np.random.default_rng(42).standard_normal((4, 32))
+    want = oracle.structure_function_grad(f.numpy().astype(np.float64), cfg["lags"], 32, G)
+    gf, gw = _run(f, cfg["lags"], 32, G, None, in_dtype="u16")
+    _check("frames", gf, want["frames"])
+    _check("window", gw, want["window"])
+
+
+@pytest.mark.parametrize("n", [16, 256])
+def test_backward_other_sizes(n):
+    require_gpu()
+    N = 24 if n == 256 else 12
+    cfg = gen.config("c1", n=n, N=N, n_bins=n // 2)
+    lags = [1, 2, 5]
+    say(f"backward: {N} frames {n}x{n} f32, Hann window, lags 1,2,5, seed 43")
+    f = gen.make_stack(cfg, 43)
+    w = _hann(n) + 0.1
+    G = np.random.default_rng(43).standard_normal((3, n // 2))
+    want = oracle.structure_function_grad(f.numpy(), lags, n // 2, G, window=w)
+    gf, gw = _run(f, lags, n // 2, G, w)
+    _check("frames", gf, want["frames"])
+    _check("window", gw, want["window"])
+
+
+def test_backward_differentiation_workload():
+    """256 float32 frames of 512x512, Hann window, lags 1, 2, 4, ..., 64,
+    256 bins: against the oracle on every pixel, and the scale invariance of
+    D (sum_x i_t dL/di_t = 0 for every frame, sum_x w dL/dw = 0)."""
+    require_gpu()
+    cfg = gen.config("c5")
+    lags = cfg["lags"]
+    assert lags == [1, 2, 4, 8, 16, 32, 64] and cfg["n_bins"] == 256
+    say("backward: 256 frames 512x512 f32 drawn on the GPU, Hann window, seed 5")
+    f = gen.make_stack(cfg, 5, device="cuda")
+    w = _hann(512)
+    G = np.random.default_rng(5).standard_normal((len(lags), 256))
+    gf, gw = _run(f, lags, 256, G, w)
+    host = f.cpu().numpy()
+    for t in (0, 100, 255):
+        dot = float((host[t].astype(np.float64) * gf[t]).sum())
+        assert abs(dot) <= 1e-4 * float(np.abs(host[t] * gf[t]).sum()), t
+    dot = float((w * gw).sum())
+    assert abs(dot) <= 1e-4 * float(np.abs(w * gw).sum())
+    say("backward: FP64 oracle adjoint of the 256 x 512^2 stack")
+    want = oracle.structure_function_grad(host, lags, 256, G, window=w)
+    _check("frames", gf, want["frames"])
+    _check("window", gw, want["window"])
+
+
+def test_autograd_function():
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfg = gen.config("c1", N=24)
+    lags = [1, 2, 4, 8]
+    say("autograd: 24 frames 128x128 f32 with a learnable window, seed 44")
+    f = gen.make_stack(cfg, 44).cuda().requires_grad_(True)
+    w = torch.from_numpy(_hann(128).astype(np.float32) + 0.05).cuda().requires_grad_(True)
+    D = nfs.structure_function(f, lags, 64, window=w)
+    G = torch.randn(D.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(44))
+    (D * G.cuda()).sum().backward()
+    ref = oracle.structure_function(f.detach().cpu().numpy(), lags, 64,
+                                    window=w.detach().cpu().numpy().astype(np.float64))
+    assert np.allclose(D.detach().cpu().numpy(), ref["D"], rtol=1e-4, atol=0)
+    want = oracle.structure_function_grad(f.detach().cpu().numpy(), lags, 64, G.numpy(),
+                                          window=w.detach().cpu().numpy().astype(np.float64))
+    _check("frames", f.grad.cpu().numpy(), want["frames"])
+    _check("window", w.grad.cpu().numpy(), want["window"])
+
+
+def test_backward_state_errors():
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    say("backward: plan without backward buffers, ring smaller than the stack")
+    f = torch.ones(6, 64, 64, device="cuda") + torch.rand(6, 64, 64, device="cuda")
+    G = torch.zeros(1, 8, dtype=torch.float64)
+    plan = nfs.Plan(64, [1], 8, in_dtype="f32", capacity=6)
+    plan.push(f)
+    with pytest.raises(nfs.NfsError) as e:
+        plan.backward(G, f)
+    assert e.value.status == 7
+    plan.close()
+    plan = nfs.Plan(64, [1], 8, in_dtype="f32", capacity=4, backward=True)
+    plan.push(f)
+    with pytest.raises(nfs.NfsError) as e:
+        plan.backward(G, f)
+    assert e.value.status == 7 and "capacity" in str(e.value)
+    plan.close()
