@@ -1,7 +1,7 @@
 """Throughput of the structure-function path on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--workload c2|c3|c5] [--spec f32|bf16|f16] [--accum plain|kahan]
+                    [--workload c2|c3|c4|c5] [--spec f32|bf16|f16] [--accum plain|kahan]
                     [--ingest device|host] [--capacity C]
 
 Default workload (c2): 1000 uint16 frames of 1024x1024 (12-bit camera model,
@@ -10,7 +10,9 @@ plain FP32 sums. c3 is the precision workload: 4000 frames of the same model
 with every lag 1..400. c5 is the differentiation workload: 256 float32
 frames of 512x512 under a Hann window, lags 1, 2, 4, ..., 64, 256 rings; its
 step also runs the gradient of a loss of D with respect to the frames and
-the window (nfs_backward). The frames are drawn on the GPU and are resident in
+the window (nfs_backward). c4 is the batching workload: 16 uint16 sequences of
+frame size 256..2048 and 200..2000 frames run together (nfs_batch_*). The
+frames are drawn on the GPU and are resident in
 HBM before timing. One step is the whole path on that stack: reset the sums,
 push the frames (normalise + 2D transform + store), accumulate the lag pairs,
 bin into D(q, tau). Prints one JSON line.
@@ -40,7 +42,11 @@ WORKLOADS = {
     "c2": "1000 uint16 frames 1024x1024, 50 log-spaced lags 1..500, 512 |q| rings",
     "c3": "4000 uint16 frames 1024x1024, lags 1..400, 512 |q| rings",
     "c5": "256 float32 frames 512x512, Hann window, lags 1,2,4,...,64, 256 |q| rings",
+    "c4": ("16 uint16 sequences, n in {256, 512, 1024, 2048}, N in [200, 2000], 32 log-spaced "
+           "lags up to N/2, n/2 |q| rings, master seed 4"),
 }
+METRIC_C4 = ("frame-pairs/sec for D(q,tau) over 16 sequences of uneven frame size and length "
+             "(batching form), 1 GPU")
 
 PAIR_COUNTERS = os.path.join(ROOT, "profiles", "pair_kernel_1000x1024_counters.md")
 PAIR_SOURCES = ["paper_1209_3362_amd/csrc/pairs.hip", "paper_1209_3362_amd/csrc/nfs_host.hpp",
@@ -84,7 +90,10 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer 5 times (known bytes), to scale "
                          "memory counters of the same profiler run")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--budget-gb", type=float, default=200.0,
+                    help="c4: memory budget of all sequences' workspaces (rings become time "
+                         "windows when the whole stacks do not fit)")
     ap.add_argument("--spec", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage type of the resident spectra")
     ap.add_argument("--accum", default="plain", choices=["plain", "kahan"],
@@ -192,6 +201,58 @@ def host_ingest(args, cfg, frames):
     }))
 
 
+def batching(args):
+    """c4: the 16 sequences analysed one after another on one stream, on
+    four streams, and as a replayed graph of the four-stream run."""
+    import torch
+    import gen
+    import paper_1209_3362_amd as nfs
+    cfgs = gen.batch_workload(master_seed=4)
+    frames = [gen.make_stack(c, c["seed"], device="cuda") for c in cfgs]
+    torch.cuda.synchronize()
+    seqs = [(c["n"], c["lags"], c["n_bins"], "u16", c["N"], "f32") for c in cfgs]
+    caps = nfs.batch_capacities(seqs, int(args.budget_gb * (1 << 30)))
+    specs = [dict(n=c["n"], lags=c["lags"], n_bins=c["n_bins"], in_dtype="u16", capacity=cap)
+             for c, cap in zip(cfgs, caps)]
+    pairs = sum(frame_pairs(c["N"], c["lags"]) for c in cfgs)
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    res = {}
+    b = nfs.Batch(specs, streams=1)
+    res["one_stream"] = timed(lambda: b.run(frames, sync=False), args.steps, args.warmup)
+    b.close()
+    del b
+    b = nfs.Batch(specs, streams=4)
+    res["four_streams"] = timed(lambda: b.run(frames, sync=False), args.steps, args.warmup)
+    outs = b.capture(frames)
+    res["four_streams_graph"] = timed(lambda: b.replay(sync=False), args.steps, args.warmup)
+    st = [int(o[3].item()) for o in outs]
+    assert all(bool(torch.isfinite(o[0]).all()) for o in outs)
+    ws = b.workspace.numel()
+    b.close()
+    best = min(res.values())
+    print(json.dumps({
+        "metric": METRIC_C4, "value": pairs / (best * 1e-3), "unit": "frame-pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": best,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["c4"], "sequences": len(cfgs),
+                   "frames": [c["N"] for c in cfgs], "n": [c["n"] for c in cfgs],
+                   "capacities": caps, "frame_pairs": pairs, "workspace_gb": ws / 1e9,
+                   "parallelism": "single GPU"},
+        "ms_per_step_by_mode": res, "status": st,
+    }))
+
+
 def differentiation(args):
     """c5: forward (push + D) and backward (nfs_backward: gradients of
     sum(G * D) for a fixed random G with respect to frames and window)."""
@@ -275,9 +336,9 @@ def main():
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
-    if args.workload == "c5":
+    if args.workload in ("c4", "c5"):
         torch.cuda.set_device(0)
-        differentiation(args)
+        (batching if args.workload == "c4" else differentiation)(args)
         return
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

@@ -7,7 +7,7 @@ same frames from here and nothing else.
 """
 from .lags import log_spaced_lags, power_of_two_lags
 from .frames import make_stack, cosine_stack
-from .configs import CONFIGS, config
+from .configs import CONFIGS, config, batch_workload
 
 __all__ = ["log_spaced_lags", "power_of_two_lags", "make_stack",
-           "cosine_stack", "CONFIGS", "config"]
+           "cosine_stack", "CONFIGS", "config", "batch_workload"]

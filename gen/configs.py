@@ -37,3 +37,28 @@ def config(name, **overrides):
     c["lags"] = list(c["lags"])
     c.update(overrides)
     return c
+
+
+def batch_workload(master_seed=4, count=16, sizes=(256, 512, 1024, 2048), frames=(200, 2000),
+                   lag_count=32):
+    """The batching workload: `count` sequences of the uint16 camera model
+    with frame size drawn from `sizes`, frame count uniform in `frames`,
+    decay-rate parameters gamma_a in [0.001, 0.01] and gamma_b in [0.1, 2]
+    (Gamma = gamma_a + gamma_b q^2) drawn from `master_seed`; `lag_count`
+    log-spaced lags up to N/2 and n/2 |q| bins per sequence. Sequence j is
+    drawn with seed 40 + j (entry "seed")."""
+    import numpy as np
+    rng = np.random.default_rng(int(master_seed))
+    out = []
+    for j in range(int(count)):
+        n = int(rng.choice(np.asarray(sizes)))
+        N = int(rng.integers(frames[0], frames[1] + 1))
+        ga = float(rng.uniform(0.001, 0.01))
+        gb = float(rng.uniform(0.1, 2.0))
+        tmax = max(1, N // 2)
+        c = config("c2", n=n, N=N, gamma_a=ga, gamma_b=gb,
+                   lags=log_spaced_lags(tmax, min(int(lag_count), tmax)), n_bins=n // 2)
+        c["name"] = f"c4/{j}"
+        c["seed"] = 40 + j
+        out.append(c)
+    return out

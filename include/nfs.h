@@ -207,6 +207,69 @@ nfs_status nfs_power_spectra_2d(nfs_handle h, float* S);
 nfs_status nfs_backward(nfs_handle h, const double* dL_dD, const void* frames,
                         float* dL_dframes, float* dL_dwindow);
 
+/* Batching form: many sequences of uneven frame size n and length N
+ * analysed together on one GPU. Each sequence has its own plan (desc), all
+ * carved from one caller-owned workspace. A run forks from the caller's
+ * stream onto up to 8 library streams (default priority), each sequence on
+ * the stream with the least work so far, most work first (work estimated
+ * from the ring capacity, taken as the expected frame count), and joins back,
+ * so small sequences fill the GPU beside large ones. The same run can be
+ * captured once into a HIP graph and replayed. Results per sequence are
+ * identical, bit for bit, to those of a single plan on the same frames. */
+typedef struct nfs_batch_s* nfs_batch_handle;
+
+/* Host only: workspace bytes of each sequence's plan (sizes, may be NULL)
+ * and of the whole batch (total, each plan aligned to 256 bytes). */
+nfs_status nfs_batch_workspace_size(const nfs_desc* descs, int32_t n_seq, size_t* sizes,
+                                    size_t* total);
+
+/* Host only: ring capacities for sequences of frames[j] frames whose
+ * workspaces must fit `budget` bytes together. Every ring holds the whole
+ * stack (capacity = max(frames, largest lag + 1)) when that fits; otherwise
+ * rings become time windows, at least the largest lag + 64 frames, sharing
+ * the rest of the budget in proportion to what each would still need
+ * (pair sums are then flushed per window). NFS_E_WORKSPACE when even the
+ * minimal windows do not fit. The descs' capacity fields are ignored. */
+nfs_status nfs_batch_capacities(const nfs_desc* descs, const int64_t* frames, int32_t n_seq,
+                                size_t budget, int64_t* capacities);
+
+/* Create a batch of n_seq plans from descs (each with its capacity set),
+ * carving `workspace` (device, 256-byte aligned, `bytes` >= the total of
+ * nfs_batch_workspace_size, owned by the caller), with n_streams worker
+ * streams (1..8); `stream` is the caller's stream runs fork from and join
+ * to. */
+nfs_status nfs_batch_create(const nfs_desc* descs, int32_t n_seq, int32_t n_streams,
+                            void* workspace, size_t bytes, void* stream,
+                            nfs_batch_handle* out);
+
+/* The plan of sequence j (owned by the batch; usable with every nfs_ call,
+ * its stream is a worker stream of the batch). */
+nfs_status nfs_batch_plan(nfs_batch_handle b, int32_t j, nfs_handle* plan);
+
+/* Enqueue one analysis of every sequence: for sequence j, reset, push
+ * counts[j] frames from frames[j] (device) and write D[j], bin_counts[j],
+ * lag_pairs[j], status[j] as nfs_structure_function does (the last three
+ * arrays, and their entries, may be NULL). Host arrays of n_seq entries.
+ * The caller's stream waits for all of it. */
+nfs_status nfs_batch_run(nfs_batch_handle b, const void* const* frames, const int64_t* counts,
+                         double* const* D, int64_t* const* bin_counts,
+                         int64_t* const* lag_pairs, int32_t* const* status);
+
+/* Capture the work of nfs_batch_run with these arguments into a HIP graph
+ * (nothing is executed; the caller's stream must not be the legacy default
+ * stream); nfs_batch_replay launches it on the caller's stream, re-reading
+ * the same frame buffers and rewriting the same outputs. Capturing again
+ * replaces the graph. */
+nfs_status nfs_batch_capture(nfs_batch_handle b, const void* const* frames,
+                             const int64_t* counts, double* const* D,
+                             int64_t* const* bin_counts, int64_t* const* lag_pairs,
+                             int32_t* const* status);
+nfs_status nfs_batch_replay(nfs_batch_handle b);
+
+/* Destroy the batch, its plans, streams and graph (the workspace stays the
+ * caller's). */
+nfs_status nfs_batch_destroy(nfs_batch_handle b);
+
 /* Forget all frames and sums (enqueued); the plan can be reused. */
 nfs_status nfs_reset(nfs_handle h);
 

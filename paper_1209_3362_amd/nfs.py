@@ -83,6 +83,20 @@ def load_library():
         "nfs_copy_spectrum": (i32, [P, i64, P]),
         "nfs_power_spectra_2d": (i32, [P, P]),
         "nfs_backward": (i32, [P, P, P, P, P]),
+        "nfs_batch_workspace_size": (i32, [ctypes.POINTER(NfsDesc), i32, ctypes.POINTER(sz),
+                                           ctypes.POINTER(sz)]),
+        "nfs_batch_capacities": (i32, [ctypes.POINTER(NfsDesc), ctypes.POINTER(i64), i32, sz,
+                                       ctypes.POINTER(i64)]),
+        "nfs_batch_create": (i32, [ctypes.POINTER(NfsDesc), i32, i32, P, sz, P,
+                                   ctypes.POINTER(P)]),
+        "nfs_batch_plan": (i32, [P, i32, ctypes.POINTER(P)]),
+        "nfs_batch_run": (i32, [P, ctypes.POINTER(P), ctypes.POINTER(i64), ctypes.POINTER(P),
+                                ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P)]),
+        "nfs_batch_capture": (i32, [P, ctypes.POINTER(P), ctypes.POINTER(i64),
+                                    ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                    ctypes.POINTER(P)]),
+        "nfs_batch_replay": (i32, [P]),
+        "nfs_batch_destroy": (i32, [P]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -328,3 +342,128 @@ def structure_function(frames, lags, n_bins, window=None, spec="f32", accum="pla
     with respect to float32 frames and the window (torch autograd)."""
     return _StructureFunction.apply(frames, window, [int(t) for t in lags], int(n_bins), spec,
                                     accum)
+
+
+def batch_capacities(seqs, budget):
+    """Ring capacities for sequences [(n, lags, n_bins, in_dtype, frames, spec)]
+    whose plans must fit `budget` bytes together (nfs_batch_capacities)."""
+    lib = load_library()
+    descs = (NfsDesc * len(seqs))()
+    keep = []
+    for j, (n, lags, nb, dt, _frames, spec) in enumerate(seqs):
+        d, arr = _desc(n, lags, nb, dt, 0, None, spec)
+        descs[j] = d
+        keep.append(arr)
+    frames = (ctypes.c_int64 * len(seqs))(*[int(q[4]) for q in seqs])
+    caps = (ctypes.c_int64 * len(seqs))()
+    st = lib.nfs_batch_capacities(descs, frames, len(seqs), ctypes.c_size_t(int(budget)), caps)
+    if st != NFS_OK:
+        raise NfsError(st, lib.nfs_status_string(st).decode())
+    return [int(c) for c in caps]
+
+
+class Batch:
+    """Many sequences analysed together (nfs_batch_*).
+
+    Batch(seqs, streams=4) with seqs = [dict(n=, lags=, n_bins=, in_dtype=,
+    capacity=, spec=)]; .run(frames_list) -> [(D, counts, pairs, status)] on
+    the device; .capture(frames_list) then .replay() for a HIP graph of the
+    same run."""
+
+    def __init__(self, seqs, streams=4, device=None, stream=None):
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the structure-function library needs one")
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        self.seqs = [dict(q) for q in seqs]
+        n_seq = len(seqs)
+        self._descs = (NfsDesc * n_seq)()
+        self._keep = []
+        for j, q in enumerate(self.seqs):
+            d, arr = _desc(q["n"], q["lags"], q["n_bins"], q.get("in_dtype", "u16"),
+                           q.get("capacity", 0), None, q.get("spec", "f32"),
+                           q.get("accum", "plain"))
+            self._descs[j] = d
+            self._keep.append(arr)
+        total = ctypes.c_size_t(0)
+        st = self.lib.nfs_batch_workspace_size(self._descs, n_seq, None, ctypes.byref(total))
+        if st != NFS_OK:
+            raise NfsError(st, self.lib.nfs_status_string(st).decode())
+        self.workspace = torch.empty(int(total.value), dtype=torch.uint8, device=self.device)
+        # A stream of its own: graphs cannot be captured on the legacy stream.
+        self.stream = stream or torch.cuda.Stream(self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.lib.nfs_batch_create(self._descs, n_seq, int(streams),
+                                           _ptr(self.workspace),
+                                           ctypes.c_size_t(self.workspace.numel()),
+                                           ctypes.c_void_p(self.stream.cuda_stream),
+                                           ctypes.byref(h))
+        if st != NFS_OK:
+            raise NfsError(st, self.lib.nfs_status_string(st).decode())
+        self.handle = h
+        self._outs = None
+        self._args = None
+
+    def _arrays(self, frames_list):
+        n_seq = len(self.seqs)
+        if len(frames_list) != n_seq:
+            raise ValueError("one frame stack per sequence")
+        P = ctypes.c_void_p
+        outs = []
+        for q, f in zip(self.seqs, frames_list):
+            dt = torch.uint16 if q.get("in_dtype", "u16") == "u16" else torch.float32
+            if f.device != self.device or f.dtype != dt or f.dim() != 3 or \
+                    tuple(f.shape[1:]) != (q["n"], q["n"]) or not f.is_contiguous():
+                raise ValueError("frames must be contiguous [count][n][n] of the sequence's "
+                                 "pixel type on the batch's device")
+            L, nb = len(q["lags"]), q["n_bins"]
+            outs.append((torch.empty((L, nb), dtype=torch.float64, device=self.device),
+                         torch.empty(nb, dtype=torch.int64, device=self.device),
+                         torch.empty(L, dtype=torch.int64, device=self.device),
+                         torch.empty(1, dtype=torch.int32, device=self.device)))
+        fr = (P * n_seq)(*[f.data_ptr() for f in frames_list])
+        cn = (ctypes.c_int64 * n_seq)(*[f.shape[0] for f in frames_list])
+        arrs = [(P * n_seq)(*[o[i].data_ptr() for o in outs]) for i in range(4)]
+        return outs, (fr, cn, *arrs)
+
+    def run(self, frames_list, sync=True):
+        outs, args = self._arrays(frames_list)
+        st = self.lib.nfs_batch_run(self.handle, *args)
+        if st != NFS_OK:
+            raise NfsError(st, self.lib.nfs_status_string(st).decode())
+        if sync:
+            self.stream.synchronize()
+        return outs
+
+    def capture(self, frames_list):
+        """Capture one run into a graph; returns the output tensors every
+        replay rewrites."""
+        outs, args = self._arrays(frames_list)
+        self.stream.synchronize()
+        st = self.lib.nfs_batch_capture(self.handle, *args)
+        if st != NFS_OK:
+            raise NfsError(st, self.lib.nfs_status_string(st).decode())
+        self._outs, self._args, self._frames = outs, args, list(frames_list)
+        return outs
+
+    def replay(self, sync=True):
+        st = self.lib.nfs_batch_replay(self.handle)
+        if st != NFS_OK:
+            raise NfsError(st, self.lib.nfs_status_string(st).decode())
+        if sync:
+            self.stream.synchronize()
+        return self._outs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.stream.synchronize()
+            self.lib.nfs_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

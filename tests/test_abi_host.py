@@ -159,12 +159,58 @@ def test_backward_reserves_its_buffers():
         assert lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out)) == want
 
 
+def test_batch_sizes_and_capacities():
+    """Batching form, host side: the batch workspace is the sum of the
+    plans' (each 256-byte aligned); ring capacities hold whole stacks when
+    the budget allows, shrink to windows of at least the largest lag + 64
+    frames under a tighter budget, and are refused below that."""
+    import gen
+    cfgs = gen.batch_workload(master_seed=4, count=16)
+    seqs = [(c["n"], c["lags"], c["n_bins"], "u16", c["N"], "f32") for c in cfgs]
+    full = [max(c["N"], c["lags"][-1] + 1) for c in cfgs]
+    sizes = [size(n=c["n"], lags=c["lags"], n_bins=c["n_bins"], in_dtype="u16", capacity=cap)
+             for c, cap in zip(cfgs, full)]
+    assert nfs.batch_capacities(seqs, 288 << 30) == full
+    assert nfs.batch_capacities(seqs, sum(sizes) + (1 << 20)) == full
+    budget = int(0.7 * sum(sizes))
+    caps = nfs.batch_capacities(seqs, budget)
+    got = [size(n=c["n"], lags=c["lags"], n_bins=c["n_bins"], in_dtype="u16", capacity=cap)
+           for c, cap in zip(cfgs, caps)]
+    assert sum(got) <= budget
+    for c, cap, f in zip(cfgs, caps, full):
+        assert min(f, c["lags"][-1] + 64) <= cap <= f
+    assert any(cap < c["N"] for cap, c in zip(caps, cfgs))
+    with pytest.raises(nfs.NfsError) as e:
+        nfs.batch_capacities(seqs, 1 << 30)
+    assert e.value.status == 5
+    lib = nfs.load_library()
+    descs = (NfsDesc * 2)()
+    keep = []
+    for j, cap in enumerate((100, 300)):
+        arr = (ctypes.c_int32 * 3)(1, 2, 50)
+        keep.append(arr)
+        descs[j] = NfsDesc(n=256, in_dtype=0, spec_dtype=0, accum=0, n_lags=3, lags=arr,
+                           n_bins=128, capacity=cap, window=None)
+    each = (ctypes.c_size_t * 2)()
+    total = ctypes.c_size_t(0)
+    assert lib.nfs_batch_workspace_size(descs, 2, each, ctypes.byref(total)) == 0
+    assert total.value == sum((v + 255) // 256 * 256 for v in each)
+    assert each[0] == size(n=256, lags=[1, 2, 50], n_bins=128, in_dtype="u16", capacity=100)
+    assert lib.nfs_batch_workspace_size(descs, 0, each, ctypes.byref(total)) == 1
+
+
 def test_calls_on_bad_handles_fail_cleanly():
     lib = nfs.load_library()
     assert lib.nfs_destroy(None) == 7
     assert lib.nfs_push_frames(None, None, 0) == 7
     assert lib.nfs_push_host_frames(None, None, 0) == 7
     assert lib.nfs_backward(None, None, None, None, None) == 7
+    assert lib.nfs_batch_destroy(None) == 7
+    assert lib.nfs_batch_replay(None) == 7
+    assert lib.nfs_batch_run(None, None, None, None, None, None, None) == 7
+    out = ctypes.c_void_p()
+    assert lib.nfs_batch_plan(None, 0, ctypes.byref(out)) == 7
+    assert lib.nfs_batch_create(None, 1, 1, None, 0, None, ctypes.byref(out)) == 1
     assert lib.nfs_structure_function(None, None, None, None, None) == 7
     assert lib.nfs_reset(None) == 7
     assert lib.nfs_last_error(None) == b"invalid handle"

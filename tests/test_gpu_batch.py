@@ -1,0 +1,112 @@
+"""Batching form on the GPU (nfs_batch_*): many sequences of uneven frame
+size and length run together on several streams, eagerly or as a replayed
+HIP graph, give per sequence exactly what a single plan gives on the same
+frames; with a memory budget that forces time-windowed rings they still
+match the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_util import assert_D_close, require_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(count=6, seed=7):
+    return gen.batch_workload(master_seed=seed, count=count, sizes=(32, 64, 128),
+                              frames=(20, 90), lag_count=8)
+
+
+def _seq(c, capacity=None):
+    return dict(n=c["n"], lags=c["lags"], n_bins=c["n_bins"], in_dtype="u16",
+                capacity=capacity or max(c["N"], c["lags"][-1] + 1))
+
+
+def _single(c, frames):
+    import paper_1209_3362_amd as nfs
+    plan = nfs.Plan(c["n"], c["lags"], c["n_bins"], in_dtype="u16",
+                    capacity=max(c["N"], c["lags"][-1] + 1))
+    plan.push(frames)
+    out = [x.cpu().numpy() for x in plan.structure_function()]
+    plan.close()
+    return out
+
+
+def _np(outs):
+    return [[x.cpu().numpy() for x in o] for o in outs]
+
+
+def test_batch_equals_single_plans():
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfgs = _small_batch()
+    say("batch: 6 sequences n in {32, 64, 128}, 20..90 u16 frames, 8 lags, 3 streams")
+    frames = [gen.make_stack(c, c["seed"], device="cuda") for c in cfgs]
+    b = nfs.Batch([_seq(c) for c in cfgs], streams=3)
+    got = _np(b.run(frames))
+    b.close()
+    for c, f, g in zip(cfgs, frames, got):
+        want = _single(c, f)
+        for x, y in zip(g, want):
+            assert np.array_equal(x, y, equal_nan=True), c["name"]
+
+
+def test_batch_graph_replays():
+    """Three replays with eager work and a change of the frame data between
+    them; every replay equals an eager batch run on the data it read."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfgs = _small_batch(count=5, seed=8)
+    say("batch graph: 5 sequences, capture once, replay 3 times")
+    frames = [gen.make_stack(c, c["seed"], device="cuda") for c in cfgs]
+    alt = [gen.make_stack(c, c["seed"] + 100, device="cuda") for c in cfgs]
+    b = nfs.Batch([_seq(c) for c in cfgs], streams=4)
+    eager = _np(b.run(frames))
+    eager_alt = _np(b.run(alt))
+    outs = b.capture(frames)
+    for rep in range(3):
+        src = alt if rep == 1 else frames
+        if rep == 1:
+            for f, a in zip(frames, alt):
+                f.copy_(a)
+        if rep == 2:
+            for j, (f, c) in enumerate(zip(frames, cfgs)):
+                f.copy_(gen.make_stack(c, c["seed"], device="cuda"))
+        torch.cuda.synchronize()
+        _ = (torch.randn(1000, device="cuda") ** 2).sum().item()  # eager work between
+        got = _np(b.replay())
+        want = eager_alt if rep == 1 else eager
+        for g, w, c in zip(got, want, cfgs):
+            for x, y in zip(g, w):
+                assert np.array_equal(x, y, equal_nan=True), (rep, c["name"])
+        del src
+    b.close()
+
+
+def test_batch_windowed_budget_matches_oracle():
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfgs = gen.batch_workload(master_seed=9, count=4, sizes=(64, 128), frames=(150, 250))
+    for c in cfgs:
+        c["lags"] = gen.log_spaced_lags(16, 6)
+    full = [max(c["N"], c["lags"][-1] + 1) for c in cfgs]
+    seqs = [(c["n"], c["lags"], c["n_bins"], "u16", c["N"], "f32") for c in cfgs]
+    sizes = [nfs.workspace_size(c["n"], c["lags"], c["n_bins"], capacity=cap)
+             for c, cap in zip(cfgs, full)]
+    budget = int(0.6 * sum(sizes))
+    caps = nfs.batch_capacities(seqs, budget)
+    say(f"batch: 4 sequences under a budget of 60% of their whole stacks, rings {caps}")
+    assert any(cap < c["N"] for cap, c in zip(caps, cfgs))
+    assert all(cap >= min(full_j, c["lags"][-1] + 64) for cap, c, full_j in zip(caps, cfgs, full))
+    frames = [gen.make_stack(c, c["seed"], device="cuda") for c in cfgs]
+    b = nfs.Batch([_seq(c, cap) for c, cap in zip(cfgs, caps)], streams=2)
+    assert b.workspace.numel() <= budget
+    got = _np(b.run(frames))
+    b.close()
+    for c, f, g in zip(cfgs, frames, got):
+        ref = oracle.structure_function(f.cpu().numpy().astype(np.float64), c["lags"],
+                                        c["n_bins"])
+        assert_D_close(g[0], ref["D"], rtol=1e-4)
+        assert np.array_equal(g[1], ref["counts"]) and np.array_equal(g[2], ref["pairs"])
