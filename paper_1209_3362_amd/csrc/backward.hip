@@ -20,6 +20,8 @@
 //       sum_t i_t * dL/du_t accumulated in FP64 in frame order.
 // Inverse transforms are forward DFTs of conjugated data: sum_k x_k
 // e^{+2 pi i jk/n} = conj(sum_k conj(x_k) e^{-2 pi i jk/n}).
+#include <algorithm>
+
 #include "fft_common.hpp"
 #include "nfs_device.hpp"
 #include "nfs_kernels.hpp"
@@ -45,14 +47,15 @@ __global__ void grad_table_kernel(int n_lags, int n_bins, const double* __restri
   gtab[i] = (tau > 0 && np > 0 && C > 0) ? float(dL_dD[i] / (double(C) * double(np))) : 0.f;
 }
 
-// Stored value of frame t at mode m, as the pair kernel pairs it.
+// Stored value of frame t at mode m, as the pair kernel pairs it. Every
+// frame of the sequence is in the ring (t < capacity), so frame t is in
+// slot t.
 template <int SPEC>
 __device__ __forceinline__ float2 stored_value(const char* __restrict__ ring,
                                                const float4* __restrict__ fscale,
                                                const float2* __restrict__ refspec,
-                                               int64_t capacity, int64_t mode_stride, int64_t t,
-                                               int64_t m) {
-  const int64_t slot = t % capacity;
+                                               int64_t mode_stride, int64_t t, int64_t m) {
+  const int64_t slot = t;
   const float4 sc = fscale[slot];
   float2 a;
   if constexpr (SPEC == kSpecF32) {
@@ -66,18 +69,25 @@ __device__ __forceinline__ float2 stored_value(const char* __restrict__ ring,
   return make_float2(fmaf(sc.y, R.x, a.x), fmaf(sc.y, R.y, a.y));
 }
 
+// One workgroup: 256 modes of one frame. Workgroups are dispatched
+// round-robin over the 8 XCDs; block b is renumbered so that each XCD walks
+// whole mode tiles frame by frame, and the spectra of frames t +- lag that
+// neighbouring frames share stay in that XCD's L2.
 template <int SPEC>
 __global__ __launch_bounds__(256) void grad_spectra_kernel(
     const char* __restrict__ ring, const float4* __restrict__ fscale,
     const float2* __restrict__ refspec, int64_t capacity, int64_t mode_stride, int64_t n_modes,
     const int32_t* __restrict__ mode_bin, const float* __restrict__ gtab,
     const int32_t* __restrict__ lags, int n_lags, int n_bins, int64_t n_frames, int64_t t0,
-    float2* __restrict__ gk) {
-  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int nframes, float2* __restrict__ gk) {
+  const int xcd = blockIdx.x % 8, local = blockIdx.x / 8;
+  const int tile = xcd + 8 * (local / nframes);
+  const int f = local % nframes;
+  const int64_t m = int64_t(tile) * 256 + threadIdx.x;
   if (m >= n_modes) return;
-  const int64_t t = t0 + blockIdx.y;
+  const int64_t t = t0 + f;
   const int b = mode_bin[m];
-  const float2 at = stored_value<SPEC>(ring, fscale, refspec, capacity, mode_stride, t, m);
+  const float2 at = stored_value<SPEC>(ring, fscale, refspec, mode_stride, t, m);
   float gx = 0.f, gy = 0.f;
   for (int l = 0; l < n_lags; ++l) {
     const float c = gtab[l * n_bins + b];
@@ -86,103 +96,142 @@ __global__ __launch_bounds__(256) void grad_spectra_kernel(
     float dx = 0.f, dy = 0.f;
     if (t + tau < n_frames) {
       const float2 o =
-          stored_value<SPEC>(ring, fscale, refspec, capacity, mode_stride, t + tau, m);
+          stored_value<SPEC>(ring, fscale, refspec, mode_stride, t + tau, m);
       dx += at.x - o.x;
       dy += at.y - o.y;
     }
     if (t >= tau) {
       const float2 o =
-          stored_value<SPEC>(ring, fscale, refspec, capacity, mode_stride, t - tau, m);
+          stored_value<SPEC>(ring, fscale, refspec, mode_stride, t - tau, m);
       dx += at.x - o.x;
       dy += at.y - o.y;
     }
     gx = fmaf(c, dx, gx);
     gy = fmaf(c, dy, gy);
   }
-  gk[int64_t(blockIdx.y) * mode_stride + m] = make_float2(2.f * gx, 2.f * gy);
+  gk[int64_t(f) * mode_stride + m] = make_float2(2.f * gx, 2.f * gy);
 }
 
-// One workgroup: CW columns k_x of one frame. Input: the stored-mode
-// gradient of the frame (zero at modes that are not stored); output
-// Z[f][y][k_x], row-major with n/2 columns.
+// One workgroup: CW columns k_x of up to `per_group` frames. Input: the
+// stored-mode gradient of each frame (zero at modes that are not stored);
+// output Z[f][y][k_x], row-major with n/2 columns. The source offsets of a
+// thread's rows are computed once; the next frame is loaded during the
+// second half of the current transform.
 template <int N>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_col_kernel(
     const float2* __restrict__ gk, int64_t mode_stride, const int32_t* __restrict__ row_width,
-    const int32_t* __restrict__ row_offset, const float2* __restrict__ tw,
-    float2* __restrict__ z) {
+    const int32_t* __restrict__ row_offset, const float2* __restrict__ tw, int nframes,
+    int per_group, float2* __restrict__ z) {
   using C = ColCfg<N>;
-  constexpr int CW = C::CW, CP = C::CP, THREADS = C::THREADS;
+  constexpr int CW = C::CW, CP = C::CP, THREADS = C::THREADS, P1 = C::P1, P2 = C::P2;
+  constexpr int GROUPS = C::GROUPS;
   __shared__ float2 lds[CW * CP];
-  __shared__ float2 twl[tw_len(N)];
-  const int f = blockIdx.y;
+  __shared__ float2 twl[C::TWL];
+  const int grp = blockIdx.x % GROUPS;
+  const int f_begin = (blockIdx.x / GROUPS) * per_group;
+  const int f_end = min(nframes, f_begin + per_group);
   const int tid = threadIdx.x;
   const int c = tid % CW, j1 = tid / CW;
-  const int kx = blockIdx.x * CW + c;
-  for (int i = tid; i < N; i += THREADS) twl[tw_skew(i)] = tw[i];
+  const int kx = grp * CW + c;
+  load_col_twiddles<N>(twl, tw, tid, THREADS);
+  int off[P2];
+#pragma unroll
+  for (int j2 = 0; j2 < P2; ++j2) {
+    const int r = j1 + P1 * j2;
+    off[j2] = kx < row_width[r] ? row_offset[r] + kx : -1;
+  }
+  auto load = [&](float2 (&v)[P2], int f) {
+    const float2* src = gk + int64_t(f) * mode_stride;
+#pragma unroll
+    for (int j2 = 0; j2 < P2; ++j2)
+      v[j2] = off[j2] >= 0 ? conjf2(src[off[j2]]) : make_float2(0.f, 0.f);
+  };
+  float2 v[P2];
+  if (f_begin < f_end) load(v, f_begin);
   __syncthreads();
-  const float2* src = gk + int64_t(f) * mode_stride;
-  float2* dst = z + int64_t(f) * N * (N / 2);
-  dft_vector<N>(
-      lds + c * CP, twl, j1,
-      [&](int r) {
-        return kx < row_width[r] ? conjf2(src[row_offset[r] + kx]) : make_float2(0.f, 0.f);
-      },
-      [&](int y, float2 X) { dst[int64_t(y) * (N / 2) + kx] = conjf2(X); });
+  float2* vec = lds + c * CP;
+  for (int f = f_begin; f < f_end; ++f) {
+    dft_first<N>(v, vec, twl, tw, j1);
+    __syncthreads();
+    if (f + 1 < f_end) load(v, f + 1);
+    float2* dst = z + int64_t(f) * N * (N / 2);
+    dft_second<N>(vec, j1, [&](int y, float2 X) { dst[int64_t(y) * (N / 2) + kx] = conjf2(X); });
+    __syncthreads();
+  }
 }
 
-// One workgroup: CW rows y of one frame. Reads Z[f][y][0..n/2), writes
-// g'[f][y][0..n) as floats over the same bytes (a row of n/2 complex values
-// and a row of n floats occupy the same bytes; every load of the row
-// precedes the workgroup barrier inside the transform, every store follows
-// it), and rowsums[f][y] = {sum_x u, sum_x g' u} with u = w * i.
+// One workgroup: CW rows y of up to `per_group` frames. Reads
+// Z[f][y][0..n/2), writes g'[f][y][0..n) as floats over the same bytes (a
+// row of n/2 complex values and a row of n floats occupy the same bytes;
+// every load of a frame's rows precedes the workgroup barrier after the
+// first half of its transform, every store follows it), and rowsums[f][y] =
+// {sum_x u, sum_x g' u} with u = w * i. The next frame's rows are loaded
+// during the second half of the current transform.
 template <int N, typename T, bool WIN>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_row_kernel(
     float2* __restrict__ z, const T* __restrict__ frames, const float* __restrict__ window,
-    const float2* __restrict__ tw, double2* __restrict__ rowsums) {
+    const float2* __restrict__ tw, int nframes, int per_group, double2* __restrict__ rowsums) {
   using C = ColCfg<N>;
-  constexpr int CW = C::CW, CP = C::CP, THREADS = C::THREADS, P1 = C::P1;
+  constexpr int CW = C::CW, CP = C::CP, THREADS = C::THREADS, P1 = C::P1, P2 = C::P2;
+  constexpr int RG = N / CW;  // row groups per frame
   __shared__ float2 lds[CW * CP];
-  __shared__ float2 twl[tw_len(N)];
+  __shared__ float2 twl[C::TWL];
   __shared__ double2 red[CW][P1];
-  const int f = blockIdx.y;
+  const int rg = blockIdx.x % RG;
+  const int f_begin = (blockIdx.x / RG) * per_group;
+  const int f_end = min(nframes, f_begin + per_group);
   const int tid = threadIdx.x;
   const int c = tid % CW, j1 = tid / CW;
-  const int y = blockIdx.x * CW + c;
-  for (int i = tid; i < N; i += THREADS) twl[tw_skew(i)] = tw[i];
-  __syncthreads();
-  const int64_t row = int64_t(f) * N + y;
-  const float2* zr = z + row * (N / 2);
-  float* gr = reinterpret_cast<float*>(z) + row * N;
-  const T* ir = frames + row * N;
-  const float* wr = WIN ? window + int64_t(y) * N : nullptr;
-  double su = 0.0, sgu = 0.0;
-  dft_vector<N>(
-      lds + c * CP, twl, j1,
-      [&](int k) {
-        if (k >= N / 2) return make_float2(0.f, 0.f);
-        const float2 v = zr[k];
-        const float s = k == 0 ? 1.f : 2.f;
-        // conj of c_k Z(y, k); at k_x = 0, Z is real (Hermitian column).
-        return k == 0 ? make_float2(v.x, 0.f) : make_float2(s * v.x, -s * v.y);
-      },
-      [&](int x, float2 X) {
-        const float g = X.x;
-        float u = float(ir[x]);
-        if constexpr (WIN) u *= wr[x];
-        su += double(u);
-        sgu += double(g) * double(u);
-        gr[x] = g;
-      });
-  red[c][j1] = make_double2(su, sgu);
-  __syncthreads();
-  if (j1 == 0) {
-    double a = 0.0, b = 0.0;
+  const int y = rg * CW + c;
+  load_col_twiddles<N>(twl, tw, tid, THREADS);
+  // Only k = j1 + P1 j2 < n/2 carry data: j2 < P2 / 2.
+  constexpr int HALF = P2 / 2;
+  auto load = [&](float2 (&v)[P2], int f) {
+    const float2* zr = z + (int64_t(f) * N + y) * (N / 2);
 #pragma unroll
-    for (int j = 0; j < P1; ++j) {
-      a += red[c][j].x;
-      b += red[c][j].y;
+    for (int j2 = 0; j2 < P2; ++j2) {
+      if (j2 < HALF) {
+        const int k = j1 + P1 * j2;
+        const float2 a = zr[k];
+        // conj of c_k Z(y, k); at k_x = 0 Z is real (Hermitian column).
+        v[j2] = k == 0 ? make_float2(a.x, 0.f) : make_float2(2.f * a.x, -2.f * a.y);
+      } else {
+        v[j2] = make_float2(0.f, 0.f);
+      }
     }
-    rowsums[row] = make_double2(a, b);
+  };
+  float2 v[P2];
+  if (f_begin < f_end) load(v, f_begin);
+  __syncthreads();
+  float2* vec = lds + c * CP;
+  const float* wr = WIN ? window + int64_t(y) * N : nullptr;
+  for (int f = f_begin; f < f_end; ++f) {
+    dft_first<N>(v, vec, twl, tw, j1);
+    __syncthreads();
+    if (f + 1 < f_end) load(v, f + 1);
+    const int64_t row = int64_t(f) * N + y;
+    float* gr = reinterpret_cast<float*>(z) + row * N;
+    const T* ir = frames + row * N;
+    double su = 0.0, sgu = 0.0;
+    dft_second<N>(vec, j1, [&](int x, float2 X) {
+      const float g = X.x;
+      float u = float(ir[x]);
+      if constexpr (WIN) u *= wr[x];
+      su += double(u);
+      sgu += double(g) * double(u);
+      gr[x] = g;
+    });
+    red[c][j1] = make_double2(su, sgu);
+    __syncthreads();
+    if (j1 == 0) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int j = 0; j < P1; ++j) {
+        a += red[c][j].x;
+        b += red[c][j].y;
+      }
+      rowsums[row] = make_double2(a, b);
+    }
   }
 }
 
@@ -223,6 +272,7 @@ __global__ __launch_bounds__(256) void finish_kernel(
   if (p >= px) return;
   const float w = WIN ? window[p] : 1.f;
   double acc = 0.0;
+#pragma unroll 4
   for (int f = 0; f < nframes; ++f) {
     const double2 s = scal[f];
     const double du = (double(gprime[int64_t(f) * px + p]) - s.y) * s.x;
@@ -244,26 +294,25 @@ hipError_t inverse_2d(int in_dtype, const float2* gk, int64_t mode_stride,
                       int nframes, float2* z, const void* frames, const float* window,
                       double2* rowsums, hipStream_t s) {
   using C = ColCfg<N>;
-  hipLaunchKernelGGL(inv_col_kernel<N>, dim3(unsigned(C::GROUPS), unsigned(nframes)),
-                     dim3(C::THREADS), 0, s, gk, mode_stride, row_width, row_offset, tw, z);
-  const dim3 grid(unsigned(N / C::CW), unsigned(nframes));
+  // About 2048 workgroups (several per CU at once, two rounds), at least one
+  // and at most 8 frames each.
+  auto per = [&](int groups) { return std::max(1, std::min(8, nframes * groups / 2048)); };
+  const int pc = per(C::GROUPS);
+  const unsigned col_blocks = unsigned(C::GROUPS * ((nframes + pc - 1) / pc));
+  hipLaunchKernelGGL(inv_col_kernel<N>, dim3(col_blocks), dim3(C::THREADS), 0, s, gk,
+                     mode_stride, row_width, row_offset, tw, nframes, pc, z);
+  constexpr int RG = N / C::CW;
+  const int pr = per(RG);
+  const dim3 grid(unsigned(RG * ((nframes + pr - 1) / pr)));
+#define NFS_INVROW_GO(T, W)                                                                   \
+  hipLaunchKernelGGL((inv_row_kernel<N, T, W>), grid, dim3(C::THREADS), 0, s, z,             \
+                     static_cast<const T*>(frames), window, tw, nframes, pr, rowsums)
   if (in_dtype == 0) {
-    auto fr = static_cast<const uint16_t*>(frames);
-    if (window)
-      hipLaunchKernelGGL((inv_row_kernel<N, uint16_t, true>), grid, dim3(C::THREADS), 0, s, z,
-                         fr, window, tw, rowsums);
-    else
-      hipLaunchKernelGGL((inv_row_kernel<N, uint16_t, false>), grid, dim3(C::THREADS), 0, s,
-                         z, fr, window, tw, rowsums);
+    if (window) NFS_INVROW_GO(uint16_t, true); else NFS_INVROW_GO(uint16_t, false);
   } else {
-    auto fr = static_cast<const float*>(frames);
-    if (window)
-      hipLaunchKernelGGL((inv_row_kernel<N, float, true>), grid, dim3(C::THREADS), 0, s, z,
-                         fr, window, tw, rowsums);
-    else
-      hipLaunchKernelGGL((inv_row_kernel<N, float, false>), grid, dim3(C::THREADS), 0, s, z,
-                         fr, window, tw, rowsums);
+    if (window) NFS_INVROW_GO(float, true); else NFS_INVROW_GO(float, false);
   }
+#undef NFS_INVROW_GO
   return hipGetLastError();
 }
 
@@ -283,12 +332,14 @@ hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
                                int64_t n_modes, const int32_t* mode_bin, const float* gtab,
                                const int32_t* lags, int n_lags, int n_bins, int64_t n_frames,
                                int64_t t0, int nframes, float2* gk, hipStream_t s) {
-  const dim3 grid(unsigned((n_modes + 255) / 256), unsigned(nframes));
+  // Mode tiles rounded up to a multiple of the 8 XCDs (see the kernel).
+  const int64_t tiles = ((n_modes + 255) / 256 + 7) / 8 * 8;
+  const dim3 grid(unsigned(tiles * nframes));
   const char* r = static_cast<const char*>(ring);
 #define NFS_GRAD_GO(SPECV)                                                                    \
   hipLaunchKernelGGL(grad_spectra_kernel<SPECV>, grid, dim3(256), 0, s, r, fscale, refspec,  \
                      capacity, mode_stride, n_modes, mode_bin, gtab, lags, n_lags, n_bins,   \
-                     n_frames, t0, gk)
+                     n_frames, t0, nframes, gk)
   if (spec == kSpecF32)
     NFS_GRAD_GO(kSpecF32);
   else if (spec == kSpecBF16)

@@ -52,14 +52,6 @@ struct RowCfg {
   static_assert(64 % P1 == 0, "a row's threads must sit in one wave");
 };
 
-// Frames one workgroup of a pass loops over: enough workgroups to give
-// every CU two, and at most 8 frames each.
-inline int frames_per_group(int nframes, int groups_per_frame) {
-  int f = (nframes * groups_per_frame) / 512;
-  if (f < 1) f = 1;
-  if (f > 8) f = 8;
-  return f;
-}
 
 // Two row-pass workgroups per CU where a thread's state fits the register
 // budget of two waves per SIMD without spilling (integer pixels, no window,
@@ -324,7 +316,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
   constexpr int WW = THREADS < 64 ? THREADS : 64;  // lanes of a (possibly partial) wave
   constexpr int NWAVES = (THREADS + 63) / 64;
   __shared__ float2 lds[CW * CP];
-  __shared__ float2 twl[tw_len(N)];
+  __shared__ float2 twl[C::TWL];
   __shared__ double red[NWAVES];
   __shared__ double red_abs[F16 ? NWAVES : 1];
 
@@ -341,7 +333,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
   const int c = tid % CW, j1 = tid / CW;
   const int kx = kx0 + c;
 
-  for (int i = tid; i < N; i += THREADS) twl[tw_skew(i)] = tw[i];
+  load_col_twiddles<N>(twl, tw, tid, THREADS);
 
   // Outputs of this thread: rows r = (j1 + q P1) + P2 k1 of column kx,
   // stored at byte offset 8 (row_offset[r] + kx) of the spectrum, or not
@@ -395,7 +387,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
     static_for<P2>([&](auto K2) {
       constexpr int k2 = decltype(K2)::value;
       float2 yv = v[bitrev<P2>(k2)];
-      if constexpr (k2 != 0) yv = cmul(yv, twl[tw_skew((j1 * k2) & (N - 1))]);
+      if constexpr (k2 != 0) yv = cmul(yv, col_twiddle<N>(twl, tw, (j1 * k2) & (N - 1)));
       col_lds[k2 * (P1 + 1) + j1] = yv;
     });
     if constexpr (!REF) {

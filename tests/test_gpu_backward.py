@@ -74,10 +74,10 @@ def test_backward_matches_oracle_u16_without_window():
     _check("window", gw, want["window"])
 
 
-@pytest.mark.parametrize("n", [16, 256])
+@pytest.mark.parametrize("n", [16, 256, 2048])
 def test_backward_other_sizes(n):
     require_gpu()
-    N = 24 if n == 256 else 12
+    N = {16: 12, 256: 24, 2048: 5}[n]
     cfg = gen.config("c1", n=n, N=N, n_bins=n // 2)
     lags = [1, 2, 5]
     say(f"backward: {N} frames {n}x{n} f32, Hann window, lags 1,2,5, seed 43")
