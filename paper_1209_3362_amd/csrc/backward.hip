@@ -87,6 +87,10 @@ __global__ __launch_bounds__(256) void grad_spectra_kernel(
   if (m >= n_modes) return;
   const int64_t t = t0 + f;
   const int b = mode_bin[m];
+  if (b < 0) {  // a slot of the tiled layout that holds no stored mode
+    gk[int64_t(f) * mode_stride + m] = make_float2(0.f, 0.f);
+    return;
+  }
   const float2 at = stored_value<SPEC>(ring, fscale, refspec, mode_stride, t, m);
   float gx = 0.f, gy = 0.f;
   for (int l = 0; l < n_lags; ++l) {
@@ -120,7 +124,7 @@ __global__ __launch_bounds__(256) void grad_spectra_kernel(
 template <int N>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_col_kernel(
     const float2* __restrict__ gk, int64_t mode_stride, const int32_t* __restrict__ row_width,
-    const int32_t* __restrict__ row_offset, const float2* __restrict__ tw, int nframes,
+    const int32_t* __restrict__ tiles, const float2* __restrict__ tw, int nframes,
     int per_group, float2* __restrict__ z) {
   using C = ColCfg<N>;
   constexpr int CW = C::CW, CP = C::CP, THREADS = C::THREADS, P1 = C::P1, P2 = C::P2;
@@ -138,7 +142,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_col_kernel(
 #pragma unroll
   for (int j2 = 0; j2 < P2; ++j2) {
     const int r = j1 + P1 * j2;
-    off[j2] = kx < row_width[r] ? row_offset[r] + kx : -1;
+    off[j2] = kx < row_width[r] ? ring_slot(N, tiles, r, kx) : -1;
   }
   auto load = [&](float2 (&v)[P2], int f) {
     const float2* src = gk + int64_t(f) * mode_stride;
@@ -290,7 +294,7 @@ __global__ void window_out_kernel(int64_t px, const double* __restrict__ gw,
 
 template <int N>
 hipError_t inverse_2d(int in_dtype, const float2* gk, int64_t mode_stride,
-                      const int32_t* row_width, const int32_t* row_offset, const float2* tw,
+                      const int32_t* row_width, const int32_t* tiles, const float2* tw,
                       int nframes, float2* z, const void* frames, const float* window,
                       double2* rowsums, hipStream_t s) {
   using C = ColCfg<N>;
@@ -300,7 +304,7 @@ hipError_t inverse_2d(int in_dtype, const float2* gk, int64_t mode_stride,
   const int pc = per(C::GROUPS);
   const unsigned col_blocks = unsigned(C::GROUPS * ((nframes + pc - 1) / pc));
   hipLaunchKernelGGL(inv_col_kernel<N>, dim3(col_blocks), dim3(C::THREADS), 0, s, gk,
-                     mode_stride, row_width, row_offset, tw, nframes, pc, z);
+                     mode_stride, row_width, tiles, tw, nframes, pc, z);
   constexpr int RG = N / C::CW;
   const int pr = per(RG);
   const dim3 grid(unsigned(RG * ((nframes + pr - 1) / pr)));
@@ -351,13 +355,13 @@ hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
 }
 
 hipError_t launch_inverse_2d(int n, int in_dtype, const float2* gk, int64_t mode_stride,
-                             const int32_t* row_width, const int32_t* row_offset,
+                             const int32_t* row_width, const int32_t* tiles,
                              const float2* tw, int nframes, float2* z, const void* frames,
                              const float* window, double2* rowsums, hipStream_t s) {
   switch (n) {
 #define NFS_INV_CASE(NV)                                                                       \
   case NV:                                                                                     \
-    return inverse_2d<NV>(in_dtype, gk, mode_stride, row_width, row_offset, tw, nframes, z,  \
+    return inverse_2d<NV>(in_dtype, gk, mode_stride, row_width, tiles, tw, nframes, z,       \
                           frames, window, rowsums, s);
     NFS_INV_CASE(16)
     NFS_INV_CASE(32)

@@ -8,6 +8,7 @@
 // per-mode table. Each half-plane mode stands for itself and its mirror -k
 // (weight 2) except on k_x = 0, where both k and -k are stored (weight 1).
 //
+// The sums are mode-major per slot of the tiled layout (ring_slot).
 // The rows of ring b are cut into segments of kSegRows rows. One
 // workgroup sums one segment: lanes are lags, so each mode's lag sums are
 // one contiguous read of the mode-major sums. A second kernel adds the
@@ -26,7 +27,7 @@ constexpr int kWaves = kThreads / 64;
 
 __global__ __launch_bounds__(kThreads) void bin_segment_kernel(
     int n, int nb, const float* __restrict__ acc, int n_lags,
-    const int32_t* __restrict__ row_offset, const int32_t* __restrict__ seg_bin,
+    const int32_t* __restrict__ tiles, const int32_t* __restrict__ seg_bin,
     const int32_t* __restrict__ seg_row0, double* __restrict__ part,
     long long* __restrict__ part_cnt) {
   using namespace dev;
@@ -53,20 +54,22 @@ __global__ __launch_bounds__(kThreads) void bin_segment_kernel(
       const int e = int(ceil_sqrt_dev(hi - ky2));
       if (e <= a) continue;
       if (l0 == 0) cnt += (a == 0) ? 1 + 2 * (e - 1) : 2 * (e - a);
-      const float* src = acc + int64_t(row_offset[ky >= 0 ? ky : ky + n]) * n_lags + l;
+      const int r = ky >= 0 ? ky : ky + n;
+      const float* src = acc + l;
+      auto at = [&](int x) { return int64_t(ring_slot(n, tiles, r, x)) * n_lags; };
       int kx = a;
       if (kx == 0) {
-        if (lag_ok) s += double(src[0]);
+        if (lag_ok) s += double(src[at(0)]);
         kx = 1;
       }
       // weight 2 for k_x > 0; four independent loads per step
       for (; kx + 4 <= e; kx += 4) {
         float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
         if (lag_ok) {
-          v0 = src[int64_t(kx) * n_lags];
-          v1 = src[int64_t(kx + 1) * n_lags];
-          v2 = src[int64_t(kx + 2) * n_lags];
-          v3 = src[int64_t(kx + 3) * n_lags];
+          v0 = src[at(kx)];
+          v1 = src[at(kx + 1)];
+          v2 = src[at(kx + 2)];
+          v3 = src[at(kx + 3)];
         }
         s += 2.0 * double(v0);
         s += 2.0 * double(v1);
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void bin_segment_kernel(
         s += 2.0 * double(v3);
       }
       for (; kx < e; ++kx)
-        if (lag_ok) s += 2.0 * double(src[int64_t(kx) * n_lags]);
+        if (lag_ok) s += 2.0 * double(src[at(kx)]);
     }
     red[wave][lane] = s;
     if (l0 == 0 && lane == 0) redc[wave] = cnt;
@@ -125,13 +128,13 @@ __global__ void bin_final_kernel(int nb, int n_lags, const double* __restrict__ 
 }  // namespace
 
 hipError_t launch_bins(int n, int n_bins, const float* acc, int n_lags,
-                       const int32_t* row_offset, const int32_t* seg_bin,
+                       const int32_t* tiles, const int32_t* seg_bin,
                        const int32_t* seg_row0, int n_segs, const int32_t* bin_seg0,
                        double* part, long long* part_cnt, const int32_t* lags,
                        int64_t n_frames, const int32_t* status, double* D, int64_t* counts,
                        int64_t* pairs, int32_t* status_out, hipStream_t s) {
   hipLaunchKernelGGL(bin_segment_kernel, dim3(unsigned(n_segs)), dim3(kThreads), 0, s, n,
-                     n_bins, acc, n_lags, row_offset, seg_bin, seg_row0, part, part_cnt);
+                     n_bins, acc, n_lags, tiles, seg_bin, seg_row0, part, part_cnt);
   const int64_t items = int64_t(n_bins) * n_lags;
   hipLaunchKernelGGL(bin_final_kernel, dim3(unsigned((items + 255) / 256)), dim3(256), 0, s,
                      n_bins, n_lags, part, part_cnt, bin_seg0, lags, n_frames, status, D,

@@ -292,8 +292,8 @@ __global__ __launch_bounds__(256) void ref_scale_kernel(int n, const double* __r
 // reference]) into ring slot (t0 + f) mod capacity, and the frame's first
 // column group writes fscale[slot] = {sigma, sigma - sigma_ref}; a frame
 // whose S is not positive and finite gets sigma = 0 and sets bit 0 of
-// *status. Both store 0 at k = 0 and only the stored modes (k_x <
-// row_width[r]); the pair kernel adds (sigma - sigma_ref) * refspec when it
+// *status. Both store 0 at k = 0 and fill the slots of the tiled layout
+// (ring_slot; n_modes slots); the pair kernel adds (sigma - sigma_ref) * refspec when it
 // reads a slot. SPEC (ring storage type): FP32 pairs; BF16 pairs rounded
 // once; FP16 pairs of sigma * 2^e * X with e the largest exponent for which
 // 2^e * sigma * (sum of the frame's rowabs) <= 65504, 2^-e written as
@@ -305,8 +305,8 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
     const double* __restrict__ rowabs, const double* __restrict__ refscal,
     float4* __restrict__ fscale, int32_t* __restrict__ status, int nframes, int per_group,
     int64_t t0, int64_t capacity, int64_t mode_stride, int64_t n_modes,
-    const int32_t* __restrict__ row_width, const int32_t* __restrict__ row_offset,
-    const float2* __restrict__ tw, char* __restrict__ ring, float2* __restrict__ refspec) {
+    const int32_t* __restrict__ tiles, const float2* __restrict__ tw, char* __restrict__ ring,
+    float2* __restrict__ refspec) {
   static_assert(!REF || SPEC == kSpecF32, "the reference transform is kept in FP32");
   constexpr bool F16 = SPEC == kSpecF16;
   constexpr uint32_t MODE_BYTES = SPEC == kSpecF32 ? 8u : 4u;
@@ -336,16 +336,17 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
   load_col_twiddles<N>(twl, tw, tid, THREADS);
 
   // Outputs of this thread: rows r = (j1 + q P1) + P2 k1 of column kx,
-  // stored at byte offset 8 (row_offset[r] + kx) of the spectrum, or not
-  // at all (kDropOffset) when kx >= row_width[r]. Up to 32 outputs per
-  // thread the offsets stay in registers across frames; more are looked up
-  // again per frame.
+  // stored at byte offset 8 ring_slot(r, kx) of the spectrum (tiled slot
+  // layout: a workgroup's columns fill one contiguous block), or not at all
+  // (kDropOffset) when the row is not kept in the column's tile. Up to 32
+  // outputs per thread the offsets stay in registers across frames; more
+  // are looked up again per frame.
   constexpr bool CACHE = Q * P1 <= 32;
   constexpr int QC = CACHE ? Q : 1, PC = CACHE ? P1 : 1;
   auto store_offset = [&](int q, int k1) -> uint32_t {
     const int r = (j1 + q * P1) + P2 * k1;
-    const int w = row_width[r], o = row_offset[r];  // both loads unconditional
-    return kx < w ? uint32_t(o + kx) * 8u : kDropOffset;
+    const int slot = ring_slot(N, tiles, r, kx);
+    return slot >= 0 ? uint32_t(slot) * 8u : kDropOffset;
   };
   uint32_t at[QC][PC];
   if constexpr (CACHE) {
@@ -505,8 +506,8 @@ hipError_t row_dispatch(int in_dtype, const void* frames, const void* ref, const
 template <int N>
 hipError_t col_launch(bool reference, int spec, const float2* inter, const double* rowsum,
                       const double* rowabs, int nframes, int64_t t0, int64_t capacity,
-                      int64_t mode_stride, int64_t n_modes, const int32_t* row_width,
-                      const int32_t* row_offset, const float2* tw, void* ring, float2* refspec,
+                      int64_t mode_stride, int64_t n_modes, const int32_t* tiles,
+                      const float2* tw, void* ring, float2* refspec,
                       double* refscal, float4* fscale, int32_t* status, hipStream_t s) {
   using C = ColCfg<N>;
   const int per = frames_per_group(nframes, C::GROUPS);
@@ -515,8 +516,8 @@ hipError_t col_launch(bool reference, int spec, const float2* inter, const doubl
 #define NFS_COL_GO(REFV, SPECV)                                                                \
   hipLaunchKernelGGL((col_pass_kernel<N, REFV, SPECV>), dim3(unsigned(blocks)),               \
                      dim3(C::THREADS), 0, s, inter, rowsum, rowabs, refscal, fscale, status,   \
-                     nframes, per, t0, capacity, mode_stride, n_modes, row_width, row_offset, \
-                     tw, ringb, refspec)
+                     nframes, per, t0, capacity, mode_stride, n_modes, tiles, tw, ringb,     \
+                     refspec)
   if (reference) {
     hipLaunchKernelGGL(ref_scale_kernel, dim3(1), dim3(256), 0, s, N, rowsum, refscal, status);
     NFS_COL_GO(true, kSpecF32);
@@ -558,13 +559,13 @@ hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* 
 hipError_t launch_col_pass(int n, bool reference, int spec, const float2* inter,
                            const double* rowsum, const double* rowabs, int nframes, int64_t t0,
                            int64_t capacity, int64_t mode_stride, int64_t n_modes,
-                           const int32_t* row_width, const int32_t* row_offset,
-                           const float2* tw, void* ring, float2* refspec, double* refscal,
-                           float4* fscale, int32_t* status, hipStream_t s) {
+                           const int32_t* tiles, const float2* tw, void* ring,
+                           float2* refspec, double* refscal, float4* fscale, int32_t* status,
+                           hipStream_t s) {
 #define NFS_COL_CASE(NN)                                                                   \
   case NN:                                                                                 \
     return col_launch<NN>(reference, spec, inter, rowsum, rowabs, nframes, t0, capacity,  \
-                          mode_stride, n_modes, row_width, row_offset, tw, ring, refspec, \
+                          mode_stride, n_modes, tiles, tw, ring, refspec,                 \
                           refscal, fscale, status, s);
   switch (n) {
     NFS_COL_CASE(16)

@@ -29,7 +29,7 @@ __global__ void bin_map_kernel(int n, int nb, int32_t* __restrict__ map) {
 // pairs (FP16 scaled by 1 / fscale.z).
 __global__ void expand_kernel(int n, const char* __restrict__ spec_base, int spec,
                               const int32_t* __restrict__ row_width,
-                              const int32_t* __restrict__ row_offset,
+                              const int32_t* __restrict__ tiles,
                               const float2* __restrict__ refspec,
                               const float4* __restrict__ fscale_slot, float2* __restrict__ out) {
   const int h = n / 2;
@@ -41,7 +41,7 @@ __global__ void expand_kernel(int n, const char* __restrict__ spec_base, int spe
     const int r = int(i / h), kx = int(i % h);
     float2 v = make_float2(0.f, 0.f);
     if (kx < row_width[r]) {
-      const int64_t at = row_offset[r] + kx;
+      const int64_t at = dev::ring_slot(n, tiles, r, kx);
       float2 a;
       if (spec == dev::kSpecF32) {
         a = reinterpret_cast<const float2*>(spec_base)[at];
@@ -63,7 +63,7 @@ __global__ void expand_kernel(int n, const char* __restrict__ spec_base, int spe
 // without pairs.
 __global__ void power_kernel(int n, int n_lags, const float* __restrict__ acc,
                              const int32_t* __restrict__ row_width,
-                             const int32_t* __restrict__ row_offset,
+                             const int32_t* __restrict__ tiles,
                              const int32_t* __restrict__ lags, int64_t n_frames,
                              float* __restrict__ out) {
   const int h = n / 2, w = h + 1;
@@ -79,7 +79,7 @@ __global__ void power_kernel(int n, int n_lags, const float* __restrict__ acc,
     if (pairs <= 0) {
       v = __builtin_nanf("");
     } else if (kx < h && kx < row_width[r]) {
-      const int64_t m = row_offset[r] + kx;
+      const int64_t m = dev::ring_slot(n, tiles, r, kx);
       v = float(double(acc[m * n_lags + l]) / double(pairs));
     }
     out[i] = v;
@@ -110,21 +110,21 @@ hipError_t launch_bin_map(int n, int n_bins, int32_t* map, hipStream_t s) {
 
 hipError_t launch_expand_spectrum(int n, const void* ring, int spec, int64_t slot,
                                   int64_t mode_stride, const int32_t* row_width,
-                                  const int32_t* row_offset, const float2* refspec,
+                                  const int32_t* tiles, const float2* refspec,
                                   const float4* fscale, float2* out, hipStream_t s) {
   const int64_t mode_bytes = spec == dev::kSpecF32 ? 8 : 4;
   const char* base = static_cast<const char*>(ring) + slot * mode_stride * mode_bytes;
   hipLaunchKernelGGL(expand_kernel, dim3(grid_for(int64_t(n) * (n / 2), 256)), dim3(256), 0, s,
-                     n, base, spec, row_width, row_offset, refspec, fscale + slot, out);
+                     n, base, spec, row_width, tiles, refspec, fscale + slot, out);
   return hipGetLastError();
 }
 
 hipError_t launch_power_spectra(int n, int n_lags, const float* acc, const int32_t* row_width,
-                                const int32_t* row_offset, const int32_t* lags,
+                                const int32_t* tiles, const int32_t* lags,
                                 int64_t n_frames, float* out, hipStream_t s) {
   hipLaunchKernelGGL(power_kernel,
                      dim3(grid_for(int64_t(n_lags) * n * (n / 2 + 1), 256)), dim3(256), 0, s, n,
-                     n_lags, acc, row_width, row_offset, lags, n_frames, out);
+                     n_lags, acc, row_width, tiles, lags, n_frames, out);
   return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ struct nfs_plan_s {
   long long* part_cnt = nullptr;
   float2* tw = nullptr;
   int32_t* width = nullptr;
-  int32_t* offset = nullptr;
+  int32_t* tiles = nullptr;     // tiled slot layout (see ring_slot)
   int32_t* lags = nullptr;
   int64_t t_pushed = 0;  // frames pushed
   int64_t t_done = 0;    // frames whose pairs (as the later frame) are summed
@@ -105,7 +105,7 @@ nfs_status flush_pairs(nfs_plan_s* h) {
   const nfs::Layout& L = h->L;
   for (const nfs::LagGroup& g : L.groups) {
     hipError_t e = nfs::launch_pairs(h->ring, L.spec_dtype, L.accum == NFS_ACC_KAHAN,
-                                     h->refspec, h->fscale, L.modes, L.mode_stride,
+                                     h->refspec, h->fscale, L.slots, L.mode_stride,
                                      L.capacity, h->t_done,
                                      h->t_pushed, h->lags + g.first, g.count, g.max_lag,
                                      h->acc + g.first, L.n_lags, g.modes, g.hist, g.waves,
@@ -161,7 +161,7 @@ nfs_status transform_batch(nfs_plan_s* h, const char* src, int64_t b) {
                              h->rowsum, nullptr, h->tw, h->stream);
     if (e == hipSuccess)
       e = nfs::launch_col_pass(L.n, true, NFS_SPEC_F32, h->inter, h->rowsum, nullptr, 1, 0,
-                               L.capacity, L.mode_stride, L.modes, h->width, h->offset, h->tw,
+                               L.capacity, L.mode_stride, L.slots, h->tiles, h->tw,
                                h->ring, h->refspec, h->refscal, h->fscale, h->status,
                                h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "reference transform launch");
@@ -170,8 +170,8 @@ nfs_status transform_batch(nfs_plan_s* h, const char* src, int64_t b) {
                            h->rowsum, h->rowabs, h->tw, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
   e = nfs::launch_col_pass(L.n, false, L.spec_dtype, h->inter, h->rowsum, h->rowabs, int(b),
-                           h->t_pushed, L.capacity, L.mode_stride, L.modes, h->width,
-                           h->offset, h->tw, h->ring, h->refspec, h->refscal, h->fscale,
+                           h->t_pushed, L.capacity, L.mode_stride, L.slots, h->tiles,
+                           h->tw, h->ring, h->refspec, h->refscal, h->fscale,
                            h->status, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
   h->t_pushed += b;
@@ -237,7 +237,7 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->status = reinterpret_cast<int32_t*>(h->ws + L.off_status);
   h->tw = reinterpret_cast<float2*>(h->ws + L.off_tw);
   h->width = reinterpret_cast<int32_t*>(h->ws + L.off_width);
-  h->offset = reinterpret_cast<int32_t*>(h->ws + L.off_offset);
+  h->tiles = reinterpret_cast<int32_t*>(h->ws + L.off_tiles);
   h->lags = reinterpret_cast<int32_t*>(h->ws + L.off_lags);
   h->refscal = reinterpret_cast<double*>(h->ws + L.off_status + 8);
   h->ref = h->ws + L.off_ref;
@@ -270,7 +270,7 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
     e = hipMemcpyAsync(h->width, L.row_width.data(), L.row_width.size() * 4,
                        hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h->offset, L.row_offset.data(), L.row_offset.size() * 4,
+    e = hipMemcpyAsync(h->tiles, L.tiles.data(), L.tiles.size() * 4,
                        hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->lags, L.lags.data(), L.lags.size() * 4, hipMemcpyHostToDevice,
@@ -386,7 +386,7 @@ nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
   nfs_status st = flush_pairs(h);
   if (st != NFS_OK) return st;
   const nfs::Layout& L = h->L;
-  hipError_t e = nfs::launch_bins(L.n, L.n_bins, h->acc, L.n_lags, h->offset, h->seg_bin,
+  hipError_t e = nfs::launch_bins(L.n, L.n_bins, h->acc, L.n_lags, h->tiles, h->seg_bin,
                                   h->seg_row0, int(L.seg_bin.size()), h->bin_seg0, h->part,
                                   h->part_cnt, h->lags, h->t_pushed, h->status, D, bin_counts,
                                   lag_pairs, status, h->stream);
@@ -400,7 +400,7 @@ nfs_status nfs_power_spectra_2d(nfs_handle h, float* S) {
   nfs_status st = flush_pairs(h);
   if (st != NFS_OK) return st;
   const nfs::Layout& L = h->L;
-  hipError_t e = nfs::launch_power_spectra(L.n, L.n_lags, h->acc, h->width, h->offset, h->lags,
+  hipError_t e = nfs::launch_power_spectra(L.n, L.n_lags, h->acc, h->width, h->tiles, h->lags,
                                            h->t_pushed, S, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "power spectra launch");
   return NFS_OK;
@@ -425,10 +425,10 @@ nfs_status nfs_backward(nfs_handle h, const double* dL_dD, const void* frames,
     const int b = int(N - t0 < L.batch ? N - t0 : L.batch);
     const char* fr = static_cast<const char*>(frames) + size_t(t0) * L.frame_bytes;
     e = nfs::launch_grad_spectra(h->ring, L.spec_dtype, h->fscale, h->refspec, L.capacity,
-                                 L.mode_stride, L.modes, h->mode_bin, h->gtab, h->lags,
+                                 L.mode_stride, L.slots, h->mode_bin, h->gtab, h->lags,
                                  L.n_lags, L.n_bins, N, t0, b, h->gk, h->stream);
     if (e == hipSuccess)
-      e = nfs::launch_inverse_2d(L.n, L.in_dtype, h->gk, L.mode_stride, h->width, h->offset,
+      e = nfs::launch_inverse_2d(L.n, L.in_dtype, h->gk, L.mode_stride, h->width, h->tiles,
                                  h->tw, b, h->inter, fr, h->window, h->brow, h->stream);
     if (e == hipSuccess)
       e = nfs::launch_grad_finish(L.n, L.in_dtype, b, h->brow, h->bscal,
@@ -482,7 +482,7 @@ nfs_status nfs_copy_spectrum(nfs_handle h, int64_t t, float* out) {
     return fail(h, NFS_E_STATE, "frame is not in the ring");
   hipError_t e = nfs::launch_expand_spectrum(h->L.n, h->ring, h->L.spec_dtype,
                                              t % h->L.capacity, h->L.mode_stride, h->width,
-                                             h->offset, h->refspec, h->fscale,
+                                             h->tiles, h->refspec, h->fscale,
                                              reinterpret_cast<float2*>(out), h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "expand launch");
   return NFS_OK;

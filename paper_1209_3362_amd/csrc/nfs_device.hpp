@@ -229,6 +229,24 @@ __device__ __forceinline__ int bin_of_dev(int n, int nb, int ky, int kx) {
   return b < uint64_t(nb) ? int(b) : -1;
 }
 
+// Slot layout of a stored spectrum: the columns k_x are cut into tiles of
+// 8; tile t keeps the transform-order rows r with |k_y(r)| <= R_t (every row
+// holding a stored mode of the tile) as consecutive runs of 8 slots, rows in
+// the order 0..R_t, n - R_t..n - 1, from slot base_t, so a column-pass
+// workgroup writes one contiguous block. tiles = {base_0 .. base_T,
+// R_0 .. R_{T-1}}, T = n / 16. Slots of rows kept but of modes that are not
+// stored (|k| >= n/2) hold the transform's values and are never binned.
+// Returns the slot of (r, kx), or -1 when row r is not kept in kx's tile.
+__device__ __forceinline__ int ring_slot(int n, const int32_t* __restrict__ tiles, int r,
+                                         int kx) {
+  const int t = kx >> 3;
+  const int R = tiles[(n >> 4) + 1 + t];
+  const int ky = r < (n >> 1) ? r : r - n;
+  if (ky > R || -ky > R) return -1;
+  const int rank = r <= R ? r : r - (n - 2 * R - 1);
+  return tiles[t] + rank * 8 + (kx & 7);
+}
+
 // Ring b = modes with lo <= |k|^2 < hi (same rule as bin_of_dev).
 __device__ __forceinline__ void ring_bounds_dev(int n, int nb, int b, int64_t* lo,
                                                 int64_t* hi) {

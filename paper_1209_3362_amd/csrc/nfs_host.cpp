@@ -149,7 +149,6 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   // Stored modes: k_x in [0, n/2), |k| < n/2; row r has k_y = r (r < n/2)
   // or r - n, and keeps k_x in [0, width).
   o.row_width.resize(o.n);
-  o.row_offset.resize(o.n);
   const int64_t hh = int64_t(o.h) * o.h;
   int64_t acc = 0;
   for (int r = 0; r < o.n; ++r) {
@@ -157,11 +156,23 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
     const int64_t rem = hh - 1 - ky * ky;
     const int w = rem < 0 ? 0 : int(isqrt_u64(uint64_t(rem))) + 1;
     o.row_width[r] = w;
-    o.row_offset[r] = int32_t(acc);
     acc += w;
   }
   o.modes = acc;
-  o.mode_stride = int64_t(align_up(size_t(acc), 64));
+  // Slots: tiles of 8 columns, each keeping the rows |k_y| <= R_t with
+  // R_t = isqrt((n/2)^2 - 1 - (8t)^2) (the rows where column 8t is stored).
+  const int T = o.n / 16;
+  o.tiles.assign(size_t(2 * T + 1), 0);
+  int64_t base = 0;
+  for (int t = 0; t < T; ++t) {
+    const int R = int(isqrt_u64(uint64_t(hh - 1 - int64_t(8 * t) * (8 * t))));
+    o.tiles[size_t(t)] = int32_t(base);
+    o.tiles[size_t(T + 1 + t)] = R;
+    base += 8 * (2 * int64_t(R) + 1);
+  }
+  o.tiles[size_t(T)] = int32_t(base);
+  o.slots = base;
+  o.mode_stride = int64_t(align_up(size_t(base), 64));
 
   // Binning segments, rings in order, kSegRows ring rows each.
   o.bin_seg0.push_back(0);
@@ -211,7 +222,7 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_status = take(kAlign);
   o.off_tw = take(size_t(o.n) * 8);
   o.off_width = take(size_t(o.n) * 4);
-  o.off_offset = take(size_t(o.n) * 4);
+  o.off_tiles = take(o.tiles.size() * 4);
   o.off_lags = take(size_t(o.n_lags) * 4);
   o.off_ref = take(o.frame_bytes);
   o.off_stage = take(o.host_staging ? 2 * size_t(o.batch) * o.frame_bytes : 0);
@@ -225,7 +236,8 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
     o.off_bin_count = take(size_t(o.n_bins) * 8);
     // Bin of every stored mode and C_b, the full-plane modes of each bin:
     // a half-plane mode with k_x > 0 stands for itself and its mirror.
-    o.mode_bin.assign(size_t(o.mode_stride), 0);
+    // Slots of modes that are not stored get -1 (no gradient).
+    o.mode_bin.assign(size_t(o.mode_stride), -1);
     o.bin_count.assign(size_t(o.n_bins), 0);
     const uint64_t nb2 = uint64_t(o.n_bins) * uint64_t(o.n_bins);
     for (int r = 0; r < o.n; ++r) {
@@ -233,7 +245,7 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
       for (int kx = 0; kx < o.row_width[r]; ++kx) {
         const uint64_t k2 = uint64_t(ky * ky) + uint64_t(kx) * uint64_t(kx);
         const int b = int(isqrt_u64(k2 * nb2) / uint64_t(o.h));
-        o.mode_bin[size_t(o.row_offset[r] + kx)] = b;
+        o.mode_bin[size_t(ring_slot_host(o, r, kx))] = b;
         o.bin_count[size_t(b)] += kx == 0 ? 1 : 2;
       }
     }
@@ -264,6 +276,16 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_fscale = o.off_ring + size_t(o.capacity) * spec_bytes;
   o.total = align_up(o.off_fscale + size_t(o.capacity) * kScaleBytes, kAlign);
   return NFS_OK;
+}
+
+int ring_slot_host(const Layout& L, int r, int kx) {
+  const int T = L.n / 16;
+  const int t = kx / 8;
+  const int R = L.tiles[size_t(T + 1 + t)];
+  const int ky = r < L.h ? r : r - L.n;
+  if (ky > R || -ky > R) return -1;
+  const int rank = r <= R ? r : r - (L.n - 2 * R - 1);
+  return L.tiles[size_t(t)] + rank * 8 + kx % 8;
 }
 
 std::vector<float> twiddle_table(int n) {

@@ -74,8 +74,9 @@ struct Layout {
   int in_dtype = 0;
   int spec_dtype = 0, accum = 0;
   int mode_bytes = 8;      // bytes per stored mode in the ring
-  int64_t modes = 0;       // M: stored modes per spectrum
-  int64_t mode_stride = 0; // M rounded up to 64: ring slot and sum-row pitch
+  int64_t modes = 0;       // M: stored modes per spectrum (those in a ring)
+  int64_t slots = 0;       // slots per spectrum in the tiled layout (>= M)
+  int64_t mode_stride = 0; // slots rounded up to 64: ring slot and sum-row pitch
   int64_t capacity = 0;    // ring slots
   int batch = 0;           // frames per transform launch
   int host_staging = 0;    // two staging buffers of `batch` frames for host pushes
@@ -84,7 +85,9 @@ struct Layout {
   int max_lag = 0;
   std::vector<int32_t> lags;
   std::vector<int32_t> row_width;   // [n] stored modes of transform-order row r
-  std::vector<int32_t> row_offset;  // [n] first stored index of row r
+  // Tiled slot layout (see ring_slot): {base_0 .. base_T, R_0 .. R_{T-1}},
+  // T = n / 16 tiles of 8 columns.
+  std::vector<int32_t> tiles;
   std::vector<LagGroup> groups;
   // Binning segments: segment s covers rows k_y in [seg_row0[s],
   // seg_row0[s] + kSegRows) of ring seg_bin[s]; ring b owns segments
@@ -92,7 +95,7 @@ struct Layout {
   std::vector<int32_t> seg_bin, seg_row0, bin_seg0;
   // Byte offsets into the workspace.
   size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_rowabs = 0, off_acc = 0;
-  size_t off_status = 0, off_tw = 0, off_width = 0, off_offset = 0;
+  size_t off_status = 0, off_tw = 0, off_width = 0, off_tiles = 0;
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
   size_t off_stage = 0;   // host-push staging: 2 x batch frames (host_staging)
   // nfs_backward (backward): k-space gradients of a batch [batch][mode_stride]
@@ -116,6 +119,10 @@ nfs_status validate_desc(const nfs_desc* d, std::string* err);
 // max_lag + 64 slots.
 nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
                        std::string* err);
+
+// Host twin of the device ring_slot: slot of (row r, column kx) in the
+// tiled layout, or -1 when the row is not kept in kx's tile.
+int ring_slot_host(const Layout& L, int r, int kx);
 
 // W_n^j = exp(-2 pi i j / n), j = 0..n-1, evaluated in double and rounded
 // once to float; interleaved (re, im).

@@ -33,13 +33,14 @@ hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* 
 // and fscale[slot] = {sigma, sigma - sigma_ref, 2^-e, 0}, with e the FP16
 // scale exponent formed from rowabs (FP16 storage) or 0. A frame whose sum
 // is not positive and finite sets bit 0 of *status and gets sigma = 0.
-// n_modes: stored modes per spectrum; only those are written.
+// n_modes: slots per spectrum in the tiled layout (tiles, see ring_slot);
+// only those are written.
 hipError_t launch_col_pass(int n, bool reference, int spec, const float2* inter,
                            const double* rowsum, const double* rowabs, int nframes, int64_t t0,
                            int64_t capacity, int64_t mode_stride, int64_t n_modes,
-                           const int32_t* row_width, const int32_t* row_offset,
-                           const float2* tw, void* ring, float2* refspec, double* refscal,
-                           float4* fscale, int32_t* status, hipStream_t s);
+                           const int32_t* tiles, const float2* tw, void* ring,
+                           float2* refspec, double* refscal, float4* fscale, int32_t* status,
+                           hipStream_t s);
 
 // Lag-pair accumulation for target frames [T0, T1) and the lags
 // lags[0..n_lags): acc[m * acc_pitch + l] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2
@@ -56,13 +57,14 @@ hipError_t launch_pairs(const void* ring, int spec, bool kahan, const float2* re
                         int n_lags, int max_lag, float* acc, int acc_pitch, int modes, int hist,
                         int waves, int per_wave, size_t lds, hipStream_t s);
 
-// Azimuthal binning from the mode-major sums acc [modes][n_lags]: segment
+// Azimuthal binning from the sums acc [slots][n_lags] (mode-major, tiled
+// slot layout: tiles, see ring_slot): segment
 // partials (segments seg_bin / seg_row0 of kSegRows ring rows), then per
 // ring D[l][b] = sum_{k in ring b} w(k) acc[k][l] / (C_b * pairs_l) in
 // double, counts[b] = C_b, pairs[l] = max(0, N - lag_l), status_out[0]
 // from *status. pairs_l == 0 gives NaN.
 hipError_t launch_bins(int n, int n_bins, const float* acc, int n_lags,
-                       const int32_t* row_offset, const int32_t* seg_bin,
+                       const int32_t* tiles, const int32_t* seg_bin,
                        const int32_t* seg_row0, int n_segs, const int32_t* bin_seg0,
                        double* part, long long* part_cnt, const int32_t* lags,
                        int64_t n_frames, const int32_t* status, double* D, int64_t* counts,
@@ -79,14 +81,14 @@ hipError_t launch_bin_map(int n, int n_bins, int32_t* map, hipStream_t s);
 // zeros where not stored.
 hipError_t launch_expand_spectrum(int n, const void* ring, int spec, int64_t slot,
                                   int64_t mode_stride, const int32_t* row_width,
-                                  const int32_t* row_offset, const float2* refspec,
+                                  const int32_t* tiles, const float2* refspec,
                                   const float4* fscale, float2* out, hipStream_t s);
 
 // P_tau(k) = acc[mode][l] / (n_frames - lags[l]) written to out
 // [n_lags][n][n/2 + 1] (0 at modes that are not stored, NaN for every mode
 // of a delay with n_frames - lag <= 0).
 hipError_t launch_power_spectra(int n, int n_lags, const float* acc, const int32_t* row_width,
-                                const int32_t* row_offset, const int32_t* lags,
+                                const int32_t* tiles, const int32_t* lags,
                                 int64_t n_frames, float* out, hipStream_t s);
 
 // Differentiation form (nfs_backward). g table: gtab[l][b] =
@@ -113,7 +115,7 @@ hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
 // [nframes][n] = {sum_x u, sum_x g' u} with u = window * frame (frames: the
 // batch's [nframes][n][n] pixels of in_dtype; window may be null).
 hipError_t launch_inverse_2d(int n, int in_dtype, const float2* gk, int64_t mode_stride,
-                             const int32_t* row_width, const int32_t* row_offset,
+                             const int32_t* row_width, const int32_t* tiles,
                              const float2* tw, int nframes, float2* z, const void* frames,
                              const float* window, double2* rowsums, hipStream_t s);
 

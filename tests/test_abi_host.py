@@ -15,6 +15,34 @@ C2_LAGS = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20
            181, 206, 234, 265, 301, 342, 388, 440, 500]
 
 
+def ring_slots(n):
+    """Slots per stored spectrum: the columns k_x < n/2 in tiles of 8, tile t
+    keeping the 2 R_t + 1 rows |k_y| <= R_t = isqrt((n/2)^2 - 1 - (8t)^2)
+    (the rows where its first column has a mode with |k| < n/2)."""
+    import math
+    h = n // 2
+    return sum(8 * (2 * math.isqrt(h * h - 1 - (8 * t) ** 2) + 1) for t in range(n // 16))
+
+
+def test_tiled_slots_hold_every_stored_mode():
+    """Every stored mode (k_x < n/2, |k| < n/2) has its tile row, so the
+    slots are at least the stored modes, with little padding at large n."""
+    import math
+    for n in (16, 64, 1024, 4096):
+        h = n // 2
+        stored = sum(math.isqrt(h * h - 1 - ky * ky) + 1 for ky in range(-h + 1, h))
+        rows = 0
+        for t in range(n // 16):
+            R = math.isqrt(h * h - 1 - (8 * t) ** 2)
+            for c in range(8):
+                kx = 8 * t + c
+                # rows of this column holding stored modes are within |k_y| <= R
+                assert h * h - 1 - kx * kx < 0 or math.isqrt(h * h - 1 - kx * kx) <= R
+            rows += 2 * R + 1
+        assert 8 * rows == ring_slots(n) >= stored
+    assert ring_slots(1024) == 415440 and 412246 < ring_slots(1024) < 1.01 * 412246
+
+
 def declared_symbols():
     text = open(os.path.join(ROOT, "include", "nfs.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
@@ -91,8 +119,7 @@ def test_storage_and_accumulation_options():
 
 
 def test_16bit_spectra_halve_the_ring():
-    modes = 412246
-    stride = (modes + 63) // 64 * 64
+    stride = (ring_slots(1024) + 63) // 64 * 64
     for spec in ("bf16", "f16"):
         a = size(n=1024, lags=C2_LAGS, n_bins=512, in_dtype="u16", capacity=1000, spec=spec)
         b = size(n=1024, lags=C2_LAGS, n_bins=512, in_dtype="u16", capacity=1001, spec=spec)
@@ -103,9 +130,8 @@ def test_16bit_spectra_halve_the_ring():
 def test_workspace_grows_with_capacity_by_one_spectrum_each():
     a = size(n=1024, lags=C2_LAGS, n_bins=512, in_dtype="u16", capacity=1000)
     b = size(n=1024, lags=C2_LAGS, n_bins=512, in_dtype="u16", capacity=1001)
-    # stored modes at n = 1024 (half disc, k_x in [0, 512)) padded to 64
-    modes = 412246
-    stride = (modes + 63) // 64 * 64
+    # slots of the tiled layout at n = 1024, padded to 64
+    stride = (ring_slots(1024) + 63) // 64 * 64
     assert b - a in (stride * 8 - 256, stride * 8, stride * 8 + 256)
     assert 3.3e9 < a < 3.6e9
 
@@ -143,9 +169,7 @@ def test_backward_reserves_its_buffers():
     a = size(n=n, lags=lags, n_bins=nb, capacity=cap)
     b = size(n=n, lags=lags, n_bins=nb, capacity=cap, backward=True)
     half = n // 2
-    M = sum(int(((half * half - 1 - ky * ky)) ** 0.5 + 1e-9) + 1
-            for ky in [r if r < half else r - n for r in range(n)] if half * half - 1 - ky * ky >= 0)
-    stride = (M + 63) // 64 * 64
+    stride = (ring_slots(n) + 63) // 64 * 64
     batch = min(1024, (128 << 20) // (n * half * 8), cap - max(lags))
     want = (up(batch * stride * 8) + up(batch * n * 16) + up(batch * 16) + up(n * n * 8)
             + up(len(lags) * nb * 4) + up(stride * 4) + up(nb * 8))
