@@ -33,6 +33,11 @@ __global__ __launch_bounds__(kThreads) void bin_segment_kernel(
   using namespace dev;
   __shared__ double red[kWaves][64];
   __shared__ long long redc[kWaves];
+  // The slot table (2 n/16 + 1 entries, at most 513) in LDS: it is read
+  // once per mode.
+  __shared__ int32_t tl[2 * (4096 / 16) + 1];
+  for (int i = threadIdx.x; i < 2 * (n / 16) + 1; i += kThreads) tl[i] = tiles[i];
+  __syncthreads();
   const int seg = blockIdx.x;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -56,7 +61,7 @@ __global__ __launch_bounds__(kThreads) void bin_segment_kernel(
       if (l0 == 0) cnt += (a == 0) ? 1 + 2 * (e - 1) : 2 * (e - a);
       const int r = ky >= 0 ? ky : ky + n;
       const float* src = acc + l;
-      auto at = [&](int x) { return int64_t(ring_slot(n, tiles, r, x)) * n_lags; };
+      auto at = [&](int x) { return int64_t(ring_slot(n, tl, r, x)) * n_lags; };
       int kx = a;
       if (kx == 0) {
         if (lag_ok) s += double(src[at(0)]);
