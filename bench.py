@@ -91,6 +91,8 @@ def parse():
                     help="only copy a 1 GiB device buffer 5 times (known bytes), to scale "
                          "memory counters of the same profiler run")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--batch-streams", type=int, default=0,
+                    help="c4: time only an eager run on this many streams (for profiling)")
     ap.add_argument("--budget-gb", type=float, default=200.0,
                     help="c4: memory budget of all sequences' workspaces (rings become time "
                          "windows when the whole stacks do not fit)")
@@ -227,6 +229,14 @@ def batching(args):
         return (time.perf_counter() - t0) * 1e3 / steps
 
     res = {}
+    if args.batch_streams:
+        b = nfs.Batch(specs, streams=args.batch_streams)
+        ms = timed(lambda: b.run(frames, sync=False), args.steps, args.warmup)
+        b.close()
+        print(json.dumps({"metric": METRIC_C4, "value": pairs / (ms * 1e-3),
+                          "unit": "frame-pairs/s", "ms_per_step": ms, "steps": args.steps,
+                          "warmup": args.warmup, "streams": args.batch_streams}))
+        return
     b = nfs.Batch(specs, streams=1)
     res["one_stream"] = timed(lambda: b.run(frames, sync=False), args.steps, args.warmup)
     b.close()
