@@ -220,8 +220,12 @@ def test_cosine_closed_form_on_gpu():
     assert np.all(np.abs(D[~hit]) < 1e-6 * want.max())
 
 
-@pytest.mark.parametrize("lags", [[1, 100, 545, 600], [3, 900, 1500]])
+@pytest.mark.parametrize("lags", [[1, 100, 545, 600], [3, 900, 1500], [2, 1200, 2400],
+                                  gen.log_spaced_lags(700, 32)])
 def test_long_lags_use_narrow_tiles(lags):
+    """Histories too long for two workgroups per CU: 16 or 8 modes per
+    workgroup, one workgroup per CU, up to the largest lag accepted (2400),
+    and 32 lags split over eight waves of four."""
     n, N = 32, max(lags) + 60
     cfg = gen.config("c1", n=n, N=N, n_bins=16)
     say(f"long lags {lags}, N={N}, 32x32")
