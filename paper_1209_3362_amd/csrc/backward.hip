@@ -116,6 +116,80 @@ __global__ __launch_bounds__(256) void grad_spectra_kernel(
   gk[int64_t(f) * mode_stride + m] = make_float2(2.f * gx, 2.f * gy);
 }
 
+// Windowed form of grad_spectra_kernel: one workgroup owns KM slots and
+// kFB target frames and first copies the spectra of frames [its first
+// target - max_lag, its last target + max_lag] of those slots, decoded, to
+// LDS (pitch KM + 1 against bank conflicts), so every spectrum is read from
+// memory and decoded once per workgroup instead of once per output and lag.
+// Thread (j, g): slot m0 + j, targets f0 + g + i (256 / KM) of the window.
+constexpr int kFB = 64;
+template <int SPEC, int KM>
+__global__ __launch_bounds__(256) void grad_spectra_lds_kernel(
+    const char* __restrict__ ring, const float4* __restrict__ fscale,
+    const float2* __restrict__ refspec, int64_t mode_stride, int64_t n_modes,
+    const int32_t* __restrict__ mode_bin, const float* __restrict__ gtab,
+    const int32_t* __restrict__ lags, int n_lags, int n_bins, int max_lag, int64_t n_frames,
+    int64_t t0, int nframes, float2* __restrict__ gk) {
+  constexpr int G = 256 / KM, KP = KM + 1, NO = kFB / G;
+  extern __shared__ float2 win[];
+  const int fblocks = (nframes + kFB - 1) / kFB;
+  const int64_t m0 = int64_t(blockIdx.x / fblocks) * KM;
+  const int f0 = (blockIdx.x % fblocks) * kFB;
+  const int64_t tfirst = t0 + f0;
+  const int64_t tlast = min(t0 + int64_t(nframes), tfirst + kFB);  // exclusive
+  const int64_t tlo = max(int64_t(0), tfirst - max_lag);
+  const int64_t thi = min(n_frames, tlast + max_lag);
+  const int rows = int(thi - tlo);
+  for (int idx = threadIdx.x; idx < rows * KM; idx += 256) {
+    const int r = idx / KM, j = idx % KM;
+    const int64_t m = m0 + j;
+    win[r * KP + j] = m < n_modes
+                          ? stored_value<SPEC>(ring, fscale, refspec, mode_stride, tlo + r, m)
+                          : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int j = threadIdx.x % KM, g = threadIdx.x / KM;
+  const int64_t m = m0 + j;
+  if (m >= n_modes) return;
+  const int b = mode_bin[m];
+  float2 acc[NO];
+#pragma unroll
+  for (int i = 0; i < NO; ++i) acc[i] = make_float2(0.f, 0.f);
+  if (b >= 0) {
+    for (int l = 0; l < n_lags; ++l) {
+      const float c = gtab[l * n_bins + b];
+      if (c == 0.f) continue;
+      const int tau = lags[l];
+#pragma unroll
+      for (int i = 0; i < NO; ++i) {
+        const int64_t t = tfirst + g + i * G;
+        if (t >= tlast) continue;
+        const int r = int(t - tlo);
+        const float2 at = win[r * KP + j];
+        float dx = 0.f, dy = 0.f;
+        if (t + tau < n_frames) {
+          const float2 o = win[(r + tau) * KP + j];
+          dx += at.x - o.x;
+          dy += at.y - o.y;
+        }
+        if (t >= tau) {
+          const float2 o = win[(r - tau) * KP + j];
+          dx += at.x - o.x;
+          dy += at.y - o.y;
+        }
+        acc[i].x = fmaf(c, dx, acc[i].x);
+        acc[i].y = fmaf(c, dy, acc[i].y);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < NO; ++i) {
+    const int64_t t = tfirst + g + i * G;
+    if (t < tlast)
+      gk[(t - t0) * mode_stride + m] = make_float2(2.f * acc[i].x, 2.f * acc[i].y);
+  }
+}
+
 // One workgroup: CW columns k_x of up to `per_group` frames. Input: the
 // stored-mode gradient of each frame (zero at modes that are not stored);
 // output Z[f][y][k_x], row-major with n/2 columns. The source offsets of a
@@ -334,8 +408,32 @@ hipError_t launch_grad_table(int n_lags, int n_bins, const double* dL_dD,
 hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
                                const float2* refspec, int64_t capacity, int64_t mode_stride,
                                int64_t n_modes, const int32_t* mode_bin, const float* gtab,
-                               const int32_t* lags, int n_lags, int n_bins, int64_t n_frames,
-                               int64_t t0, int nframes, float2* gk, hipStream_t s) {
+                               const int32_t* lags, int n_lags, int n_bins, int max_lag,
+                               int64_t n_frames, int64_t t0, int nframes, float2* gk,
+                               hipStream_t s) {
+  // The windowed kernel when a window of kFB targets plus the lags either
+  // side fits 64 KB of LDS with 32, 16 or 8 slots per workgroup.
+  const int64_t rows = kFB + 2 * int64_t(max_lag);
+  const int fblocks = (nframes + kFB - 1) / kFB;
+  const char* rr = static_cast<const char*>(ring);
+#define NFS_GRADW_GO(SPECV, KMV)                                                              \
+  hipLaunchKernelGGL((grad_spectra_lds_kernel<SPECV, KMV>),                                   \
+                     dim3(unsigned(((n_modes + KMV - 1) / KMV) * fblocks)), dim3(256),         \
+                     size_t(rows) * (KMV + 1) * 8, s, rr, fscale, refspec, mode_stride,        \
+                     n_modes, mode_bin, gtab, lags, n_lags, n_bins, max_lag, n_frames, t0,     \
+                     nframes, gk)
+#define NFS_GRADW_KM(KMV)                                                                     \
+  if (rows * (KMV + 1) * 8 <= 64 * 1024) {                                                    \
+    if (spec == kSpecF32) NFS_GRADW_GO(kSpecF32, KMV);                                        \
+    else if (spec == kSpecBF16) NFS_GRADW_GO(kSpecBF16, KMV);                                 \
+    else NFS_GRADW_GO(kSpecF16, KMV);                                                         \
+    return hipGetLastError();                                                                 \
+  }
+  NFS_GRADW_KM(32)
+  NFS_GRADW_KM(16)
+  NFS_GRADW_KM(8)
+#undef NFS_GRADW_KM
+#undef NFS_GRADW_GO
   // Mode tiles rounded up to a multiple of the 8 XCDs (see the kernel).
   const int64_t tiles = ((n_modes + 255) / 256 + 7) / 8 * 8;
   const dim3 grid(unsigned(tiles * nframes));

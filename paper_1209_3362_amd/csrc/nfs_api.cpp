@@ -426,7 +426,7 @@ nfs_status nfs_backward(nfs_handle h, const double* dL_dD, const void* frames,
     const char* fr = static_cast<const char*>(frames) + size_t(t0) * L.frame_bytes;
     e = nfs::launch_grad_spectra(h->ring, L.spec_dtype, h->fscale, h->refspec, L.capacity,
                                  L.mode_stride, L.slots, h->mode_bin, h->gtab, h->lags,
-                                 L.n_lags, L.n_bins, N, t0, b, h->gk, h->stream);
+                                 L.n_lags, L.n_bins, L.max_lag, N, t0, b, h->gk, h->stream);
     if (e == hipSuccess)
       e = nfs::launch_inverse_2d(L.n, L.in_dtype, h->gk, L.mode_stride, h->width, h->tiles,
                                  h->tw, b, h->inter, fr, h->window, h->brow, h->stream);

@@ -105,8 +105,9 @@ hipError_t launch_grad_table(int n_lags, int n_bins, const double* dL_dD,
 hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
                                const float2* refspec, int64_t capacity, int64_t mode_stride,
                                int64_t n_modes, const int32_t* mode_bin, const float* gtab,
-                               const int32_t* lags, int n_lags, int n_bins, int64_t n_frames,
-                               int64_t t0, int nframes, float2* gk, hipStream_t s);
+                               const int32_t* lags, int n_lags, int n_bins, int max_lag,
+                               int64_t n_frames, int64_t t0, int nframes, float2* gk,
+                               hipStream_t s);
 
 // Adjoint of the 2D transform for nframes frames: inverse column transforms
 // of gk (stored modes, [nframes][mode_stride]) into z [nframes][n][n/2]

@@ -90,6 +90,23 @@ def test_backward_other_sizes(n):
     _check("window", gw, want["window"])
 
 
+@pytest.mark.parametrize("lags", [[1, 3, 60], [2, 450]])
+def test_backward_window_and_global_gradient_kernels(lags):
+    """Short lags take the LDS-windowed k-space gradient kernel; a largest
+    lag of 450 needs more history than its LDS holds and takes the
+    global-memory kernel."""
+    require_gpu()
+    N = lags[-1] + 30
+    cfg = gen.config("c1", n=32, N=N, n_bins=16)
+    say(f"backward: {N} frames 32x32 f32, lags {lags}, seed 45")
+    f = gen.make_stack(cfg, 45)
+    G = np.random.default_rng(45).standard_normal((len(lags), 16))
+    want = oracle.structure_function_grad(f.numpy(), lags, 16, G)
+    gf, gw = _run(f, lags, 16, G, None, chunk=97)
+    _check("frames", gf, want["frames"])
+    _check("window", gw, want["window"])
+
+
 def test_backward_differentiation_workload():
     """256 float32 frames of 512x512, Hann window, lags 1, 2, 4, ..., 64,
     256 bins: against the oracle on every pixel, and the scale invariance of
