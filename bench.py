@@ -418,6 +418,23 @@ def main():
     bytes_spec = N * M * (8 if args.spec == "f32" else 4)
     bytes_sums = len(lags) * M * 4
     alg_bytes = bytes_frames + 2 * bytes_spec + 2 * bytes_sums
+    # Serial-stage floor of this design: the transform's HBM bytes (frames
+    # read, spectra written) at the HBM peak, 4 VALU lane-instructions per
+    # pair-k at the issue rate, the binning's sums read at the HBM peak.
+    floor_ms = ((bytes_frames + bytes_spec) / (HBM_PEAK_GBPS * 1e9)
+                + 4.0 * pairs * M / VALU_LANE_OPS + bytes_sums / (HBM_PEAK_GBPS * 1e9)) * 1e3
+    # Achievable copy bandwidth on this GPU now: 1 GiB device-to-device.
+    src = torch.ones((1 << 28,), dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * (1 << 30) / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
     pair_k = pairs * M
     # Pair kernel: per pair and mode 2 subtractions + 2 FMAs = 6 FLOP
     # (4 VALU lane-instructions; the Kahan form adds a few per chunk).
@@ -441,6 +458,10 @@ def main():
                    "frame_pairs": pairs, "stored_modes": M, "spectra": args.spec,
                    "accumulation": args.accum, "parallelism": "single GPU"},
         "hbm_gbps_algorithmic": alg_bytes / (ms_step * 1e-3) / 1e9,
+        "hbm_frac_algorithmic": alg_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+        "copy_gbps_measured": copy_gbps,
+        "serial_floor_ms": floor_ms,
+        "frac_of_serial_floor": floor_ms / ms_step,
         "stage_ms": {"normalise_fft_store": ms_fft, "lag_pairs": ms_pair, "bin": ms_bin},
         "status": st,
         "roofline": {
