@@ -110,3 +110,24 @@ def test_batch_windowed_budget_matches_oracle():
                                         c["n_bins"])
         assert_D_close(g[0], ref["D"], rtol=1e-4)
         assert np.array_equal(g[1], ref["counts"]) and np.array_equal(g[2], ref["pairs"])
+
+
+def test_batch_workload_full_size_equals_single_plans():
+    """The 16-sequence workload the benchmark times (n 256..2048, 200..2000
+    frames, 32 lags each), run as one four-stream batch, equals single plans
+    on the same frames bit for bit for every sequence."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfgs = gen.batch_workload(master_seed=4)
+    say("batch full size: 16 sequences drawn on the GPU (master seed 4), four streams")
+    frames = [gen.make_stack(c, c["seed"], device="cuda") for c in cfgs]
+    b = nfs.Batch([_seq(c) for c in cfgs], streams=4)
+    got = _np(b.run(frames))
+    b.close()
+    del b
+    for c, f, g in zip(cfgs, frames, got):
+        say(f"batch full size: single plan for {c['name']} (n {c['n']}, {c['N']} frames)")
+        want = _single(c, f)
+        for x, y in zip(g, want):
+            assert np.array_equal(x, y, equal_nan=True), c["name"]
+        assert g[3] == 0
