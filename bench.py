@@ -104,6 +104,8 @@ def parse():
                     help="device: frames resident in HBM before timing (the metric); host: "
                          "frames in pinned host memory, uploaded inside the timed step "
                          "through the plan's staging buffers (streaming ingest)")
+    ap.add_argument("--tune", action="store_true",
+                    help="tune the pair kernel's launch shape on the stack before timing")
     ap.add_argument("--capacity", type=int, default=0,
                     help="ring slots (0 = the number of frames)")
     ap.add_argument("--frames-cache", default=None,
@@ -229,6 +231,7 @@ def batching(args):
         return (time.perf_counter() - t0) * 1e3 / steps
 
     res = {}
+    tuned = None
     if args.batch_streams:
         b = nfs.Batch(specs, streams=args.batch_streams)
         ms = timed(lambda: b.run(frames, sync=False), args.steps, args.warmup)
@@ -242,6 +245,9 @@ def batching(args):
     b.close()
     del b
     b = nfs.Batch(specs, streams=4)
+    if args.tune:
+        tuned = b.tune(frames)
+        torch.cuda.synchronize()
     res["four_streams"] = timed(lambda: b.run(frames, sync=False), args.steps, args.warmup)
     outs = b.capture(frames)
     res["four_streams_graph"] = timed(lambda: b.replay(sync=False), args.steps, args.warmup)
@@ -258,7 +264,8 @@ def batching(args):
         "config": {"workload": WORKLOADS["c4"], "sequences": len(cfgs),
                    "frames": [c["N"] for c in cfgs], "n": [c["n"] for c in cfgs],
                    "capacities": caps, "frame_pairs": pairs, "workspace_gb": ws / 1e9,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "pair_shapes": "four-stream runs tuned %s" % tuned if tuned else "planned"},
         "ms_per_step_by_mode": res, "status": st,
     }))
 
@@ -374,6 +381,11 @@ def main():
     stream = plan.stream
     out = plan.empty_outputs()
     M = plan.modes
+    tuned = None
+    if args.tune:
+        plan.push(frames)
+        tuned = plan.tune_pairs()
+        plan.reset()
     pairs = frame_pairs(N, lags)
 
     def step(ev=None):
@@ -456,7 +468,8 @@ def main():
         "config": {"workload": WORKLOADS[args.workload] + ", seed %d" % args.seed,
                    "frames": N, "n": n, "lags": len(lags), "n_bins": nb,
                    "frame_pairs": pairs, "stored_modes": M, "spectra": args.spec,
-                   "accumulation": args.accum, "parallelism": "single GPU"},
+                   "accumulation": args.accum, "parallelism": "single GPU",
+                   "pair_shapes": "tuned %s" % tuned if tuned else "planned"},
         "hbm_gbps_algorithmic": alg_bytes / (ms_step * 1e-3) / 1e9,
         "hbm_frac_algorithmic": alg_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS,
         "copy_gbps_measured": copy_gbps,

@@ -155,6 +155,21 @@ nfs_status nfs_push_frames(nfs_handle h, const void* frames, int64_t count);
  * NFS_E_STATE. count == 0 is a no-op. */
 nfs_status nfs_push_host_frames(nfs_handle h, const void* frames, int64_t count);
 
+/* Empirical tuning of the pair kernel's launch shape (modes per workgroup
+ * and waves summing lags) for each group of lags: times every shape the
+ * kernel supports on the frames pushed so far (all of them while the ring
+ * holds them all, else the frames whose partners are all still resident;
+ * sums go to scratch memory, the plan's sums are not touched) and keeps the
+ * fastest for the plan's later pair sums. The choice
+ * made at plan time is a fixed rule; tuning can differ from it for unusual
+ * lag sets and frame sizes. Synchronises the plan's stream. choices: host
+ * int32 [2 * groups] receiving (modes, waves) per group, or NULL; groups:
+ * host int32 receiving the number of lag groups, or NULL. NFS_E_STATE when
+ * fewer than 2 frames were pushed. Tuned plans give the same D within the
+ * FP32 sum tolerance (16 and 8 modes per workgroup split a mode's frames
+ * over different lanes), not bit for bit. */
+nfs_status nfs_tune_pairs(nfs_handle h, int32_t* choices, int32_t* groups);
+
 /* Accumulate the pair sums of every frame pushed so far (enqueued). Needed
  * only to split the work, e.g. to overlap it with acquisition or to time it:
  * nfs_structure_function does it implicitly. */

@@ -44,6 +44,7 @@ struct nfs_plan_s {
   int32_t* width = nullptr;
   int32_t* tiles = nullptr;     // tiled slot layout (see ring_slot)
   int32_t* lags = nullptr;
+  std::vector<nfs::LagGroup> groups;  // pair launch shapes (layout's, or tuned)
   int64_t t_pushed = 0;  // frames pushed
   int64_t t_done = 0;    // frames whose pairs (as the later frame) are summed
   // Host pushes (host_staging): two device staging buffers of one batch;
@@ -103,7 +104,7 @@ nfs_status hip_fail(nfs_plan_s* h, hipError_t e, const char* where) {
 nfs_status flush_pairs(nfs_plan_s* h) {
   if (h->t_done >= h->t_pushed) return NFS_OK;
   const nfs::Layout& L = h->L;
-  for (const nfs::LagGroup& g : L.groups) {
+  for (const nfs::LagGroup& g : h->groups) {
     hipError_t e = nfs::launch_pairs(h->ring, L.spec_dtype, L.accum == NFS_ACC_KAHAN,
                                      h->refspec, h->fscale, L.slots, L.mode_stride,
                                      L.capacity, h->t_done,
@@ -225,6 +226,7 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
     return st;
   }
   const nfs::Layout& L = h->L;
+  h->groups = L.groups;
   h->stream = static_cast<hipStream_t>(stream);
   h->ws = static_cast<char*>(workspace);
   h->window = desc->window;
@@ -371,6 +373,65 @@ nfs_status nfs_push_host_frames(nfs_handle h, const void* frames, int64_t count)
     h->freed_recorded[j] = true;
     i += b;
   }
+  return NFS_OK;
+}
+
+nfs_status nfs_tune_pairs(nfs_handle h, int32_t* choices, int32_t* groups) {
+  if (!is_live(h)) return NFS_E_STATE;
+  const nfs::Layout& L = h->L;
+  if (h->t_pushed < 2) return fail(h, NFS_E_STATE, "tuning needs at least 2 pushed frames");
+  // Target window [T0, T1): every pushed frame when the ring still holds
+  // them all (the window a pair flush of the whole stack covers), else the
+  // frames whose partners are all still in the ring.
+  const int64_t T1 = h->t_pushed;
+  const int64_t T0 = T1 <= L.capacity ? 0 : T1 - (L.capacity - L.max_lag);
+  // Scratch sums in the row-pass intermediate (dead between pushes): the
+  // first slots that fit, in whole workgroup tiles.
+  const int64_t inter_bytes = int64_t(L.batch) * L.n * L.h * 8;
+  int64_t slots = inter_bytes / (int64_t(L.n_lags) * 4);
+  if (slots > L.slots) slots = L.slots;
+  slots = slots / 16 * 16;
+  if (slots < 16) return fail(h, NFS_E_STATE, "no scratch room for tuning");
+  float* scratch = reinterpret_cast<float*>(h->inter);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (size_t gi = 0; e == hipSuccess && gi < h->groups.size(); ++gi) {
+    const nfs::LagGroup cur = h->groups[gi];
+    float best_ms = 0.f;
+    nfs::LagGroup best = cur;
+    for (const nfs::LagGroup& c : nfs::group_candidates(L.lags, cur.first, cur.count)) {
+      auto go = [&]() {
+        return nfs::launch_pairs(h->ring, L.spec_dtype, L.accum == NFS_ACC_KAHAN, h->refspec,
+                                 h->fscale, slots, L.mode_stride, L.capacity, T0, T1,
+                                 h->lags + c.first, c.count, c.max_lag, scratch + c.first,
+                                 L.n_lags, c.modes, c.hist, c.waves, c.per_wave, c.lds,
+                                 h->stream);
+      };
+      e = go();  // warm-up
+      if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+      if (e == hipSuccess) e = go();
+      if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) break;
+      if (best_ms == 0.f || ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+    }
+    if (e == hipSuccess) h->groups[gi] = best;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(h, e, "pair tuning");
+  if (groups) *groups = int32_t(h->groups.size());
+  if (choices)
+    for (size_t gi = 0; gi < h->groups.size(); ++gi) {
+      choices[2 * gi] = h->groups[gi].modes;
+      choices[2 * gi + 1] = h->groups[gi].waves;
+    }
   return NFS_OK;
 }
 

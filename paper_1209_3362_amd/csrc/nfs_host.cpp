@@ -126,6 +126,33 @@ static bool plan_group(const std::vector<int32_t>& lags, int first, int count,
   return best_w > 0;
 }
 
+std::vector<LagGroup> group_candidates(const std::vector<int32_t>& lags, int first, int count) {
+  std::vector<LagGroup> out;
+  const int S = kPairChunk;
+  const int max_lag = lags[first + count - 1];
+  const int H = int(align_up(size_t(max_lag + 2 * S), S));
+  for (int K : {16, 8}) {
+    const size_t lds = size_t(H + kPairMirror) * K * 8;
+    if (lds > size_t(kLdsBytes)) continue;
+    for (int W = 1; W <= kMaxPairWaves; ++W) {
+      const int per = (count + W - 1) / W;
+      if (per > kMaxLagsPerWave) continue;
+      if (W > 8 && per < 6) continue;
+      LagGroup g;
+      g.first = first;
+      g.count = count;
+      g.max_lag = max_lag;
+      g.modes = K;
+      g.hist = H;
+      g.lds = lds;
+      g.waves = W;
+      g.per_wave = per;
+      out.push_back(g);
+    }
+  }
+  return out;
+}
+
 nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
                        std::string* err) {
   nfs_status st = validate_desc(d, err);

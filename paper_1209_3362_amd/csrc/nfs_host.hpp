@@ -111,6 +111,12 @@ struct Layout {
   size_t off_lags = 0, total = 0;
 };
 
+// Every launch shape the pair kernel can run a lag group of `count` lags
+// from lags[first] with: 16 or 8 modes per workgroup (LDS for two
+// workgroups per CU, or for one), and each wave count whose slices fit
+// (at most kMaxLagsPerWave lags per wave; 12-wave workgroups for 6 or more).
+std::vector<LagGroup> group_candidates(const std::vector<int32_t>& lags, int first, int count);
+
 // Validates `d`; on failure returns the status and fills `err`.
 nfs_status validate_desc(const nfs_desc* d, std::string* err);
 

@@ -73,6 +73,7 @@ def load_library():
         "nfs_push_frames": (i32, [P, P, i64]),
         "nfs_push_host_frames": (i32, [P, P, i64]),
         "nfs_accumulate": (i32, [P]),
+        "nfs_tune_pairs": (i32, [P, P, ctypes.POINTER(i32)]),
         "nfs_structure_function": (i32, [P, P, P, P, P]),
         "nfs_reset": (i32, [P]),
         "nfs_destroy": (i32, [P]),
@@ -222,6 +223,16 @@ class Plan:
         """Wait for the plan's stream; releases borrowed host frames."""
         self.stream.synchronize()
         self._borrowed.clear()
+
+    def tune_pairs(self):
+        """nfs_tune_pairs: time every pair-kernel launch shape on the frames
+        pushed so far and keep the fastest; returns [(modes, waves)] per lag
+        group. Synchronises the plan's stream."""
+        n = ctypes.c_int32(0)
+        self._check(self.lib.nfs_tune_pairs(self.handle, None, ctypes.byref(n)))
+        arr = (ctypes.c_int32 * (2 * n.value))()
+        self._check(self.lib.nfs_tune_pairs(self.handle, arr, ctypes.byref(n)))
+        return [(arr[2 * i], arr[2 * i + 1]) for i in range(n.value)]
 
     def accumulate(self):
         """Sum the pairs of every frame pushed so far (enqueued)."""
@@ -427,6 +438,27 @@ class Batch:
         cn = (ctypes.c_int64 * n_seq)(*[f.shape[0] for f in frames_list])
         arrs = [(P * n_seq)(*[o[i].data_ptr() for o in outs]) for i in range(4)]
         return outs, (fr, cn, *arrs)
+
+    def tune(self, frames_list):
+        """Tune every sequence's pair-kernel launch shape on its frames
+        (push, nfs_tune_pairs, reset per plan); returns the shapes."""
+        self._arrays(frames_list)  # validates shapes and types
+        shapes = []
+        for j, f in enumerate(frames_list):
+            p = ctypes.c_void_p()
+            st = self.lib.nfs_batch_plan(self.handle, j, ctypes.byref(p))
+            if st == NFS_OK:
+                st = self.lib.nfs_push_frames(p, _ptr(f), ctypes.c_int64(f.shape[0]))
+            n = ctypes.c_int32(0)
+            arr = (ctypes.c_int32 * 64)()
+            if st == NFS_OK:
+                st = self.lib.nfs_tune_pairs(p, arr, ctypes.byref(n))
+            if st == NFS_OK:
+                st = self.lib.nfs_reset(p)
+            if st != NFS_OK:
+                raise NfsError(st, self.lib.nfs_last_error(p).decode())
+            shapes.append([(arr[2 * i], arr[2 * i + 1]) for i in range(n.value)])
+        return shapes
 
     def run(self, frames_list, sync=True):
         outs, args = self._arrays(frames_list)

@@ -262,3 +262,33 @@ def test_bad_calls_raise():
     plan.close()
     with pytest.raises(nfs.NfsError):
         nfs.Plan(32, [1, 1], 16, in_dtype="u16", capacity=8)
+
+
+def test_tuned_pair_shapes_keep_parity():
+    """nfs_tune_pairs times every launch shape on the pushed frames, keeps
+    the fastest, and leaves the plan's sums untouched; D afterwards meets
+    the oracle."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfg = gen.config("c2", n=128, N=300, lags=gen.log_spaced_lags(250, 40), n_bins=64)
+    say("tuning: 300 frames 128x128 u16, 40 log-spaced lags to 250, seed 46")
+    f = gen.make_stack(cfg, 46)
+    ref = oracle.structure_function(f.numpy().astype(np.float64), cfg["lags"], 64)
+    plan = nfs.Plan(128, cfg["lags"], 64, in_dtype="u16", capacity=300)
+    g = f.cuda()
+    plan.push(g[:150])
+    shapes = plan.tune_pairs()
+    assert shapes and all(m in (16, 8) and 1 <= w <= 12 for m, w in shapes)
+    plan.push(g[150:])
+    D, C, P, st = plan.structure_function()
+    plan.close()
+    assert int(st.item()) == 0
+    assert np.array_equal(P.cpu().numpy(), ref["pairs"])
+    assert_D_close(D.cpu().numpy(), ref["D"], rtol=1e-4)
+    print("tuned shapes", shapes)
+    plan = nfs.Plan(128, cfg["lags"], 64, in_dtype="u16", capacity=300)
+    plan.push(g[:1])
+    with pytest.raises(nfs.NfsError) as e:
+        plan.tune_pairs()
+    assert e.value.status == 7
+    plan.close()
