@@ -35,14 +35,13 @@ struct nfs_batch_s {
   hipGraphExec_t exec = nullptr;
 
   ~nfs_batch_s() {
+    // Let enqueued work finish before its plans and streams go away.
+    for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     for (nfs_handle p : plans)
       if (p) (void)nfs_destroy(p);
-    for (hipStream_t s : streams) {
-      (void)hipStreamSynchronize(s);
-      (void)hipStreamDestroy(s);
-    }
+    for (hipStream_t s : streams) (void)hipStreamDestroy(s);
     if (fork) (void)hipEventDestroy(fork);
     for (hipEvent_t e : join)
       if (e) (void)hipEventDestroy(e);
