@@ -107,6 +107,26 @@ def test_backward_window_and_global_gradient_kernels(lags):
     _check("window", gw, want["window"])
 
 
+@pytest.mark.parametrize("spec,tol", [("bf16", 3e-2), ("f16", 3e-3)])
+def test_backward_from_16bit_spectra(spec, tol):
+    """With 16-bit resident spectra the k-space gradient uses the decoded
+    stored values (the gradient of the D computed from them); against the
+    exact adjoint the error is set by the storage rounding (8 or 11
+    significant bits of fluctuation-sized values), orders of magnitude below
+    what a wrong decode, scale or reference correction would give."""
+    require_gpu()
+    cfg = gen.config("c1", N=40)
+    lags = [1, 2, 4, 8, 16]
+    say(f"backward from {spec} spectra: 40 frames 128x128 f32, Hann window, seed 47")
+    f = gen.make_stack(cfg, 47)
+    w = _hann(128) + 0.1
+    G = np.random.default_rng(47).standard_normal((len(lags), 64))
+    want = oracle.structure_function_grad(f.numpy(), lags, 64, G, window=w)
+    gf, gw = _run(f, lags, 64, G, w, spec=spec)
+    _check("frames", gf, want["frames"], tol=tol)
+    _check("window", gw, want["window"], tol=tol)
+
+
 def test_backward_differentiation_workload():
     """256 float32 frames of 512x512, Hann window, lags 1, 2, 4, ..., 64,
     256 bins: against the oracle on every pixel, and the scale invariance of
