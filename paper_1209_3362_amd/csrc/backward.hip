@@ -192,7 +192,8 @@ __global__ __launch_bounds__(256) void grad_spectra_lds_kernel(
 
 // One workgroup: CW columns k_x of up to `per_group` frames. Input: the
 // stored-mode gradient of each frame (zero at modes that are not stored);
-// output Z[f][y][k_x], row-major with n/2 columns. The source offsets of a
+// output Z[f][tile][y][TWD] (tiles of TWD columns, one per workgroup, so
+// each workgroup writes one contiguous block). The source offsets of a
 // thread's rows are computed once; the next frame is loaded during the
 // second half of the current transform.
 template <int N>
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_col_kernel(
     int per_group, float2* __restrict__ z) {
   using C = ColCfg<N>;
   constexpr int CW = C::CW, CP = C::CP, THREADS = C::THREADS, P1 = C::P1, P2 = C::P2;
-  constexpr int GROUPS = C::GROUPS;
+  constexpr int GROUPS = C::GROUPS, TILES = C::TILES, TWD = C::TWD;
   __shared__ float2 lds[CW * CP];
   __shared__ float2 twl[C::TWL];
   const int grp = blockIdx.x % GROUPS;
@@ -232,25 +233,25 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_col_kernel(
     dft_first<N>(v, vec, twl, tw, j1);
     __syncthreads();
     if (f + 1 < f_end) load(v, f + 1);
-    float2* dst = z + int64_t(f) * N * (N / 2);
-    dft_second<N>(vec, j1, [&](int y, float2 X) { dst[int64_t(y) * (N / 2) + kx] = conjf2(X); });
+    float2* dst = z + (int64_t(f) * TILES + kx / TWD) * N * TWD + kx % TWD;
+    dft_second<N>(vec, j1, [&](int y, float2 X) { dst[int64_t(y) * TWD] = conjf2(X); });
     __syncthreads();
   }
 }
 
-// One workgroup: CW rows y of up to `per_group` frames. Reads
-// Z[f][y][0..n/2), writes g'[f][y][0..n) as floats over the same bytes (a
-// row of n/2 complex values and a row of n floats occupy the same bytes;
-// every load of a frame's rows precedes the workgroup barrier after the
-// first half of its transform, every store follows it), and rowsums[f][y] =
-// {sum_x u, sum_x g' u} with u = w * i. The next frame's rows are loaded
-// during the second half of the current transform.
+// One workgroup: CW rows y of up to `per_group` frames. Reads the rows of
+// Z (tiled as inv_col_kernel writes it, so a wave's loads cover whole
+// CW-row blocks of tiles), writes g'[f][y][0..n) as floats, and
+// rowsums[f][y] = {sum_x u, sum_x g' u} with u = w * i. The next frame's
+// rows are loaded during the second half of the current transform.
 template <int N, typename T, bool WIN>
 __global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_row_kernel(
-    float2* __restrict__ z, const T* __restrict__ frames, const float* __restrict__ window,
-    const float2* __restrict__ tw, int nframes, int per_group, double2* __restrict__ rowsums) {
+    const float2* __restrict__ z, float* __restrict__ gprime, const T* __restrict__ frames,
+    const float* __restrict__ window, const float2* __restrict__ tw, int nframes,
+    int per_group, double2* __restrict__ rowsums) {
   using C = ColCfg<N>;
   constexpr int CW = C::CW, CP = C::CP, THREADS = C::THREADS, P1 = C::P1, P2 = C::P2;
+  constexpr int TILES = C::TILES, TWD = C::TWD;
   constexpr int RG = N / CW;  // row groups per frame
   __shared__ float2 lds[CW * CP];
   __shared__ float2 twl[C::TWL];
@@ -265,12 +266,12 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_row_kernel(
   // Only k = j1 + P1 j2 < n/2 carry data: j2 < P2 / 2.
   constexpr int HALF = P2 / 2;
   auto load = [&](float2 (&v)[P2], int f) {
-    const float2* zr = z + (int64_t(f) * N + y) * (N / 2);
+    const float2* zf = z + int64_t(f) * TILES * N * TWD + int64_t(y) * TWD;
 #pragma unroll
     for (int j2 = 0; j2 < P2; ++j2) {
       if (j2 < HALF) {
         const int k = j1 + P1 * j2;
-        const float2 a = zr[k];
+        const float2 a = zf[int64_t(k / TWD) * N * TWD + k % TWD];
         // conj of c_k Z(y, k); at k_x = 0 Z is real (Hermitian column).
         v[j2] = k == 0 ? make_float2(a.x, 0.f) : make_float2(2.f * a.x, -2.f * a.y);
       } else {
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS) void inv_row_kernel(
     __syncthreads();
     if (f + 1 < f_end) load(v, f + 1);
     const int64_t row = int64_t(f) * N + y;
-    float* gr = reinterpret_cast<float*>(z) + row * N;
+    float* gr = gprime + row * N;
     const T* ir = frames + row * N;
     double su = 0.0, sgu = 0.0;
     dft_second<N>(vec, j1, [&](int x, float2 X) {
@@ -369,8 +370,8 @@ __global__ void window_out_kernel(int64_t px, const double* __restrict__ gw,
 template <int N>
 hipError_t inverse_2d(int in_dtype, const float2* gk, int64_t mode_stride,
                       const int32_t* row_width, const int32_t* tiles, const float2* tw,
-                      int nframes, float2* z, const void* frames, const float* window,
-                      double2* rowsums, hipStream_t s) {
+                      int nframes, float2* z, float* gprime, const void* frames,
+                      const float* window, double2* rowsums, hipStream_t s) {
   using C = ColCfg<N>;
   // About 2048 workgroups (several per CU at once, two rounds), at least one
   // and at most 8 frames each.
@@ -383,7 +384,7 @@ hipError_t inverse_2d(int in_dtype, const float2* gk, int64_t mode_stride,
   const int pr = per(RG);
   const dim3 grid(unsigned(RG * ((nframes + pr - 1) / pr)));
 #define NFS_INVROW_GO(T, W)                                                                   \
-  hipLaunchKernelGGL((inv_row_kernel<N, T, W>), grid, dim3(C::THREADS), 0, s, z,             \
+  hipLaunchKernelGGL((inv_row_kernel<N, T, W>), grid, dim3(C::THREADS), 0, s, z, gprime,     \
                      static_cast<const T*>(frames), window, tw, nframes, pr, rowsums)
   if (in_dtype == 0) {
     if (window) NFS_INVROW_GO(uint16_t, true); else NFS_INVROW_GO(uint16_t, false);
@@ -454,13 +455,14 @@ hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
 
 hipError_t launch_inverse_2d(int n, int in_dtype, const float2* gk, int64_t mode_stride,
                              const int32_t* row_width, const int32_t* tiles,
-                             const float2* tw, int nframes, float2* z, const void* frames,
-                             const float* window, double2* rowsums, hipStream_t s) {
+                             const float2* tw, int nframes, float2* z, float* gprime,
+                             const void* frames, const float* window, double2* rowsums,
+                             hipStream_t s) {
   switch (n) {
 #define NFS_INV_CASE(NV)                                                                       \
   case NV:                                                                                     \
     return inverse_2d<NV>(in_dtype, gk, mode_stride, row_width, tiles, tw, nframes, z,       \
-                          frames, window, rowsums, s);
+                          gprime, frames, window, rowsums, s);
     NFS_INV_CASE(16)
     NFS_INV_CASE(32)
     NFS_INV_CASE(64)

@@ -490,10 +490,11 @@ nfs_status nfs_backward(nfs_handle h, const double* dL_dD, const void* frames,
                                  L.n_lags, L.n_bins, L.max_lag, N, t0, b, h->gk, h->stream);
     if (e == hipSuccess)
       e = nfs::launch_inverse_2d(L.n, L.in_dtype, h->gk, L.mode_stride, h->width, h->tiles,
-                                 h->tw, b, h->inter, fr, h->window, h->brow, h->stream);
+                                 h->tw, b, h->inter, reinterpret_cast<float*>(h->gk), fr,
+                                 h->window, h->brow, h->stream);
     if (e == hipSuccess)
       e = nfs::launch_grad_finish(L.n, L.in_dtype, b, h->brow, h->bscal,
-                                  reinterpret_cast<const float*>(h->inter), fr, h->window,
+                                  reinterpret_cast<const float*>(h->gk), fr, h->window,
                                   dL_dframes ? dL_dframes + size_t(t0) * px : nullptr,
                                   dL_dwindow ? h->gw : nullptr, h->stream);
   }

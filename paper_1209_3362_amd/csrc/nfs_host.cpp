@@ -254,7 +254,8 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_ref = take(o.frame_bytes);
   o.off_stage = take(o.host_staging ? 2 * size_t(o.batch) * o.frame_bytes : 0);
   if (o.backward) {
-    o.off_gk = take(size_t(o.batch) * o.mode_stride * 8);
+    // k-space gradients of a batch, later its g' images (n x n floats).
+    o.off_gk = take(size_t(o.batch) * std::max(size_t(o.mode_stride) * 8, size_t(o.n) * o.n * 4));
     o.off_brow = take(size_t(o.batch) * o.n * 16);
     o.off_bscal = take(size_t(o.batch) * 16);
     o.off_gw = take(size_t(o.n) * o.n * 8);

@@ -99,7 +99,8 @@ struct Layout {
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
   size_t off_stage = 0;   // host-push staging: 2 x batch frames (host_staging)
   // nfs_backward (backward): k-space gradients of a batch [batch][mode_stride]
-  // complex, per-row sums [batch][n] and per-frame scalars [batch] (two
+  // complex (the same region later holds its g' images [batch][n][n] floats),
+  // per-row sums [batch][n] and per-frame scalars [batch] (two
   // doubles each), window gradient [n][n] FP64, g table [n_lags][n_bins],
   // bin of every stored mode [mode_stride], full-plane modes per bin.
   size_t off_gk = 0, off_brow = 0, off_bscal = 0, off_gw = 0, off_gtab = 0;

@@ -110,15 +110,17 @@ hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
                                hipStream_t s);
 
 // Adjoint of the 2D transform for nframes frames: inverse column transforms
-// of gk (stored modes, [nframes][mode_stride]) into z [nframes][n][n/2]
-// complex, then per row the real inverse transform with the half-plane
-// weights, written over z as g' [nframes][n][n] floats, and rowsums
+// of gk (stored modes, [nframes][mode_stride]) into z (n x n/2 complex per
+// frame, in tiles of the column transform's workgroup width), then per row
+// the real inverse transform with the half-plane weights into gprime
+// [nframes][n][n] floats (may alias gk: gk is read before), and rowsums
 // [nframes][n] = {sum_x u, sum_x g' u} with u = window * frame (frames: the
 // batch's [nframes][n][n] pixels of in_dtype; window may be null).
 hipError_t launch_inverse_2d(int n, int in_dtype, const float2* gk, int64_t mode_stride,
                              const int32_t* row_width, const int32_t* tiles,
-                             const float2* tw, int nframes, float2* z, const void* frames,
-                             const float* window, double2* rowsums, hipStream_t s);
+                             const float2* tw, int nframes, float2* z, float* gprime,
+                             const void* frames, const float* window, double2* rowsums,
+                             hipStream_t s);
 
 // Adjoint of the normalisation and window product for nframes frames:
 // scal[f] = {1/m, mean(g' i')}; dL_dframes[f] = w (g' - mean(g' i')) / m

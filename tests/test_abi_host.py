@@ -160,7 +160,8 @@ def test_host_staging_adds_two_batches_of_frames():
 
 def test_backward_reserves_its_buffers():
     """Differentiation form: one batch of k-space gradients (mode_stride
-    complex each), per-row sums (16 B per row), per-frame scalars, an FP64
+    complex each, or the frame's n x n floats of g' if larger, which reuse
+    the region), per-row sums (16 B per row), per-frame scalars, an FP64
     window gradient, the g table, the mode-bin table and the bin counts, each
     rounded up to 256 bytes."""
     def up(v):
@@ -171,7 +172,7 @@ def test_backward_reserves_its_buffers():
     half = n // 2
     stride = (ring_slots(n) + 63) // 64 * 64
     batch = min(1024, (128 << 20) // (n * half * 8), cap - max(lags))
-    want = (up(batch * stride * 8) + up(batch * n * 16) + up(batch * 16) + up(n * n * 8)
+    want = (up(batch * max(stride * 8, n * n * 4)) + up(batch * n * 16) + up(batch * 16) + up(n * n * 8)
             + up(len(lags) * nb * 4) + up(stride * 4) + up(nb * 8))
     assert b - a == want
     lib = nfs.load_library()
