@@ -49,8 +49,10 @@ METRIC_C4 = ("frame-pairs/sec for D(q,tau) over 16 sequences of uneven frame siz
              "(batching form), 1 GPU")
 
 PAIR_COUNTERS = os.path.join(ROOT, "profiles", "pair_kernel_1000x1024_counters.md")
-PAIR_SOURCES = ["paper_1209_3362_amd/csrc/pairs.hip", "paper_1209_3362_amd/csrc/nfs_host.hpp",
-                "paper_1209_3362_amd/csrc/nfs_host.cpp"]
+# What shapes the pair kernel's memory traffic: the kernel, its device
+# helpers and its launch planner.
+PAIR_SOURCES = ["paper_1209_3362_amd/csrc/pairs.hip", "paper_1209_3362_amd/csrc/nfs_device.hpp",
+                "paper_1209_3362_amd/csrc/pair_plan.hpp", "paper_1209_3362_amd/csrc/pair_plan.cpp"]
 
 
 def pair_source_digest():

@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnfs.so")
 
 HIP_SOURCES = ["fft.hip", "pairs.hip", "bins.hip", "misc.hip", "backward.hip"]
-CPP_SOURCES = ["nfs_host.cpp", "nfs_api.cpp", "nfs_batch.cpp"]
+CPP_SOURCES = ["pair_plan.cpp", "nfs_host.cpp", "nfs_api.cpp", "nfs_batch.cpp"]
 ARCH = "gfx950"
 
 

@@ -9,26 +9,13 @@
 #include <vector>
 
 #include "nfs.h"
+#include "pair_plan.hpp"
 
 namespace nfs {
 
 constexpr int kMinN = 16;
 constexpr int kMaxN = 4096;
 constexpr size_t kAlign = 256;
-// Frames of the time series handled per step of the pair kernel (with K
-// modes per workgroup every lane holds 32 * K / 64 target frames).
-constexpr int kPairChunk = 32;
-// Most lags one wave of the pair kernel accumulates at once, and most waves
-// per workgroup; a launch handles at most their product.
-constexpr int kMaxLagsPerWave = 8;
-constexpr int kMaxPairWaves = 12;
-// LDS rows mirrored after the pair kernel's history ring: from a row of the
-// ring a lane reads up to S + kMaxLagsPerWave - 2 rows further on.
-constexpr int kPairMirror = kPairChunk + kMaxLagsPerWave;
-// LDS a workgroup may allocate on gfx950.
-constexpr int kLdsBytes = 160 * 1024;
-// Largest delay the pair kernel's on-chip history supports (K = 8 modes).
-constexpr int kMaxLag = 2400;
 // Ring rows summed by one workgroup of the binning pass.
 constexpr int kSegRows = 64;
 // Target size of the row-transform intermediate of one batch of frames.
@@ -51,23 +38,6 @@ int64_t ceil_sqrt_i64(int64_t v);
 int bin_of(int n, int nb, int ky, int kx);
 // Ring b holds the modes with lo <= |k|^2 < hi.
 void ring_bounds(int n, int nb, int b, int64_t* lo, int64_t* hi);
-
-// One group of lags handled by one launch of the pair kernel.
-// Lags of the busiest SIMD when `count` lags are split over `waves` waves
-// in contiguous slices whose lengths differ by at most one (the first
-// count % waves waves take one more) and wave w runs on SIMD w % 4.
-int pair_simd_load(int count, int waves);
-
-struct LagGroup {
-  int first = 0;      // index of the group's first lag in the lag list
-  int count = 0;      // lags in the group
-  int max_lag = 0;    // largest lag of the group
-  int modes = 0;      // K: modes per workgroup
-  int hist = 0;       // H: history rows kept in LDS (multiple of the chunk)
-  int waves = 0;      // waves that sum lags (the launch has 8, or 12 if more)
-  int per_wave = 0;   // most lags of one wave (<= kMaxLagsPerWave)
-  size_t lds = 0;     // dynamic LDS bytes
-};
 
 struct Layout {
   int n = 0, h = 0, n_bins = 0, n_lags = 0;
@@ -111,12 +81,6 @@ struct Layout {
   size_t off_segs = 0, off_part = 0, off_part_cnt = 0;
   size_t off_lags = 0, total = 0;
 };
-
-// Every launch shape the pair kernel can run a lag group of `count` lags
-// from lags[first] with: 16 or 8 modes per workgroup (LDS for two
-// workgroups per CU, or for one), and each wave count whose slices fit
-// (at most kMaxLagsPerWave lags per wave; 12-wave workgroups for 6 or more).
-std::vector<LagGroup> group_candidates(const std::vector<int32_t>& lags, int first, int count);
 
 // Validates `d`; on failure returns the status and fills `err`.
 nfs_status validate_desc(const nfs_desc* d, std::string* err);

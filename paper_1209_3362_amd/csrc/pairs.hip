@@ -23,7 +23,7 @@
 // every difference. The correction is applied once per (frame, mode) as the
 // slot is copied into LDS.
 #include "nfs_device.hpp"
-#include "nfs_host.hpp"
+#include "pair_plan.hpp"
 #include "nfs_kernels.hpp"
 
 namespace nfs {
