@@ -47,6 +47,9 @@ struct nfs_plan_s {
   std::vector<nfs::LagGroup> groups;  // pair launch shapes (layout's, or tuned)
   int64_t t_pushed = 0;  // frames pushed
   int64_t t_done = 0;    // frames whose pairs (as the later frame) are summed
+  // No pair launch since the sums were reset: the next one stores its sums
+  // instead of adding them, so a reset needs no fill of the sums.
+  bool sums_fresh = true;
   // Host pushes (host_staging): two device staging buffers of one batch;
   // copies run on `copy`, transforms on `stream`. copied[j] marks batch
   // data in buffer j, freed[j] the end of the transform that read it.
@@ -109,19 +112,31 @@ nfs_status flush_pairs(nfs_plan_s* h) {
                                      h->refspec, h->fscale, L.slots, L.mode_stride,
                                      L.capacity, h->t_done,
                                      h->t_pushed, h->lags + g.first, g.count, g.max_lag,
-                                     h->acc + g.first, L.n_lags, g.modes, g.hist, g.waves,
-                                     g.per_wave, g.lds, h->stream);
+                                     h->acc + g.first, L.n_lags, h->sums_fresh, g.modes,
+                                     g.hist, g.waves, g.per_wave, g.lds, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "pair kernel launch");
   }
+  h->sums_fresh = false;
   h->t_done = h->t_pushed;
   return NFS_OK;
 }
 
-nfs_status clear_sums(nfs_plan_s* h) {
+// Sums ready for reading: pending pairs summed, and zeros where no pair
+// launch has run since the reset (no frames pushed).
+nfs_status finish_sums(nfs_plan_s* h) {
+  nfs_status st = flush_pairs(h);
+  if (st != NFS_OK || !h->sums_fresh) return st;
   const nfs::Layout& L = h->L;
   hipError_t e = nfs::launch_fill_u32(h->acc, size_t(L.n_lags) * L.mode_stride, 0u, h->stream);
-  if (e == hipSuccess) e = nfs::launch_fill_u32(h->status, 1, 0u, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "fill kernel launch");
+  h->sums_fresh = false;
+  return NFS_OK;
+}
+
+nfs_status clear_sums(nfs_plan_s* h) {
+  hipError_t e = nfs::launch_fill_u32(h->status, 1, 0u, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "fill kernel launch");
+  h->sums_fresh = true;
   h->t_pushed = 0;
   h->t_done = 0;
   return NFS_OK;
@@ -405,7 +420,7 @@ nfs_status nfs_tune_pairs(nfs_handle h, int32_t* choices, int32_t* groups) {
         return nfs::launch_pairs(h->ring, L.spec_dtype, L.accum == NFS_ACC_KAHAN, h->refspec,
                                  h->fscale, slots, L.mode_stride, L.capacity, T0, T1,
                                  h->lags + c.first, c.count, c.max_lag, scratch + c.first,
-                                 L.n_lags, c.modes, c.hist, c.waves, c.per_wave, c.lds,
+                                 L.n_lags, true, c.modes, c.hist, c.waves, c.per_wave, c.lds,
                                  h->stream);
       };
       e = go();  // warm-up
@@ -444,7 +459,7 @@ nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
                                   int64_t* lag_pairs, int32_t* status) {
   if (!is_live(h)) return NFS_E_STATE;
   if (!D) return fail(h, NFS_E_ARG, "D is NULL");
-  nfs_status st = flush_pairs(h);
+  nfs_status st = finish_sums(h);
   if (st != NFS_OK) return st;
   const nfs::Layout& L = h->L;
   hipError_t e = nfs::launch_bins(L.n, L.n_bins, h->acc, L.n_lags, h->tiles, h->seg_bin,
@@ -458,7 +473,7 @@ nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
 nfs_status nfs_power_spectra_2d(nfs_handle h, float* S) {
   if (!is_live(h)) return NFS_E_STATE;
   if (!S) return fail(h, NFS_E_ARG, "S is NULL");
-  nfs_status st = flush_pairs(h);
+  nfs_status st = finish_sums(h);
   if (st != NFS_OK) return st;
   const nfs::Layout& L = h->L;
   hipError_t e = nfs::launch_power_spectra(L.n, L.n_lags, h->acc, h->width, h->tiles, h->lags,

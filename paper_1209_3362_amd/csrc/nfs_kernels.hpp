@@ -44,7 +44,8 @@ hipError_t launch_col_pass(int n, bool reference, int spec, const float2* inter,
 
 // Lag-pair accumulation for target frames [T0, T1) and the lags
 // lags[0..n_lags): acc[m * acc_pitch + l] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2
-// over t in [T0, T1) with t - lag >= 0 (acc is mode-major), where
+// over t in [T0, T1) with t - lag >= 0 (acc is mode-major; with `assign`
+// the sums are stored instead, for modes m < n_modes), where
 // I_t = decoded ring slot of t + fscale[slot].y * refspec (refspec has
 // mode_stride entries, 0 at k = 0; the ring stores `spec`-typed modes,
 // FP16 ones scaled by 1 / fscale[slot].z). Frames [max(0, T0 - max lag), T1)
@@ -54,8 +55,9 @@ hipError_t launch_col_pass(int n, bool reference, int spec, const float2* inter,
 hipError_t launch_pairs(const void* ring, int spec, bool kahan, const float2* refspec,
                         const float4* fscale, int64_t n_modes, int64_t mode_stride,
                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
-                        int n_lags, int max_lag, float* acc, int acc_pitch, int modes, int hist,
-                        int waves, int per_wave, size_t lds, hipStream_t s);
+                        int n_lags, int max_lag, float* acc, int acc_pitch, bool assign,
+                        int modes, int hist, int waves, int per_wave, size_t lds,
+                        hipStream_t s);
 
 // Azimuthal binning from the sums acc [slots][n_lags] (mode-major, tiled
 // slot layout: tiles, see ring_slot): segment

@@ -46,7 +46,7 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
     const char* __restrict__ ring, int spec, const float2* __restrict__ refspec,
     const float4* __restrict__ fscale, int64_t n_modes, int64_t mode_stride, int64_t capacity,
     int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags, int max_lag,
-    float* __restrict__ acc, int acc_pitch, int H, int lag_waves) {
+    float* __restrict__ acc, int acc_pitch, bool assign, int H, int lag_waves) {
   static_assert(K == 16 || K == 8, "16 or 8 modes per workgroup");
   constexpr int S = kPairChunk;  // frames per chunk
   constexpr int G = 64 / K;         // lanes sharing one mode inside a wave
@@ -384,7 +384,8 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
 
   // Lanes g = 0..G-1 of one mode hold partial sums over disjoint frames;
   // their total goes through LDS so the workgroup adds its K x n_lags block
-  // to the mode-major sums acc[mode][lag] with contiguous accesses.
+  // to the mode-major sums acc[mode][lag] with contiguous accesses (or
+  // stores it, `assign`, for the first window after the sums were reset).
   __syncthreads();  // every wave is done with the history
   float* blk = reinterpret_cast<float*>(hist4);  // [K][n_lags]
 #pragma unroll
@@ -401,7 +402,8 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
   const int nel = int(kmax) * n_lags;
   for (int e = threadIdx.x; e < nel; e += nthreads) {
     const int mm = e / n_lags, l = e - mm * n_lags;
-    acc[(m0 + mm) * acc_pitch + l] += blk[e];
+    float* dst = acc + (m0 + mm) * acc_pitch + l;
+    *dst = assign ? blk[e] : *dst + blk[e];
   }
 }
 
@@ -409,7 +411,8 @@ template <int K, int P, int NW, bool KAHAN>
 hipError_t pair_launch(const char* ring, int spec, const float2* refspec, const float4* fscale,
                        int64_t n_modes, int64_t mode_stride, int64_t capacity, int64_t T0,
                        int64_t T1, const int32_t* lags, int n_lags, int max_lag, float* acc,
-                       int acc_pitch, int hist, int waves, size_t lds, hipStream_t s) {
+                       int acc_pitch, bool assign, int hist, int waves, size_t lds,
+                       hipStream_t s) {
   // Allow the LDS history beyond the default dynamic limit; a failure here
   // shows up as a launch error below.
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_kernel<K, P, NW, KAHAN>),
@@ -417,7 +420,7 @@ hipError_t pair_launch(const char* ring, int spec, const float2* refspec, const 
   const int64_t blocks = (n_modes + K - 1) / K;
   hipLaunchKernelGGL((pair_kernel<K, P, NW, KAHAN>), dim3(unsigned(blocks)), dim3(64 * NW), lds,
                      s, ring, spec, refspec, fscale, n_modes, mode_stride, capacity, T0, T1,
-                     lags, n_lags, max_lag, acc, acc_pitch, hist, waves);
+                     lags, n_lags, max_lag, acc, acc_pitch, assign, hist, waves);
   return hipGetLastError();
 }
 
@@ -427,12 +430,12 @@ template <int K, bool KAHAN>
 hipError_t pair_dispatch(int per_wave, const char* ring, int spec, const float2* refspec,
                          const float4* fscale, int64_t n_modes, int64_t mode_stride,
                          int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
-                         int n_lags, int max_lag, float* acc, int acc_pitch, int hist, int waves,
-                         size_t lds, hipStream_t s) {
+                         int n_lags, int max_lag, float* acc, int acc_pitch, bool assign,
+                         int hist, int waves, size_t lds, hipStream_t s) {
 #define NFS_PAIR_P(PP, NWW)                                                                 \
   return pair_launch<K, PP, NWW, KAHAN>(ring, spec, refspec, fscale, n_modes, mode_stride, \
                                         capacity, T0, T1, lags, n_lags, max_lag, acc,       \
-                                        acc_pitch, hist, waves, lds, s)
+                                        acc_pitch, assign, hist, waves, lds, s)
   if (waves <= 8) {
     switch (per_wave) {
       case 1: NFS_PAIR_P(1, 8);
@@ -463,13 +466,14 @@ hipError_t pair_dispatch(int per_wave, const char* ring, int spec, const float2*
 hipError_t launch_pairs(const void* ring, int spec, bool kahan, const float2* refspec,
                         const float4* fscale, int64_t n_modes, int64_t mode_stride,
                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
-                        int n_lags, int max_lag, float* acc, int acc_pitch, int modes, int hist,
-                        int waves, int per_wave, size_t lds, hipStream_t s) {
+                        int n_lags, int max_lag, float* acc, int acc_pitch, bool assign,
+                        int modes, int hist, int waves, int per_wave, size_t lds,
+                        hipStream_t s) {
   const char* r = static_cast<const char*>(ring);
 #define NFS_PAIR_CASE(KK, KH)                                                              \
   return pair_dispatch<KK, KH>(per_wave, r, spec, refspec, fscale, n_modes, mode_stride,  \
                                capacity, T0, T1, lags, n_lags, max_lag, acc, acc_pitch,   \
-                               hist, waves, lds, s)
+                               assign, hist, waves, lds, s)
   if (modes == 16) {
     if (kahan) NFS_PAIR_CASE(16, true);
     NFS_PAIR_CASE(16, false);
