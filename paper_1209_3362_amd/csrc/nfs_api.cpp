@@ -35,9 +35,9 @@ struct nfs_plan_s {
   void* ref = nullptr;          // reference frame: first frame of the sequence
   float2* refspec = nullptr;    // its transform on the stored modes
   float4* fscale = nullptr;     // per ring slot: {sigma, sigma - sigma_ref, 2^-e, 0}
-  int32_t* seg_bin = nullptr;   // binning segments (see nfs::Layout)
-  int32_t* seg_row0 = nullptr;
+  int32_t* seg_first = nullptr;  // binning table and segments (see nfs::Layout)
   int32_t* bin_seg0 = nullptr;
+  int32_t* bin_slots = nullptr;
   double* part = nullptr;       // per-segment partial sums [segments][lags]
   long long* part_cnt = nullptr;
   float2* tw = nullptr;
@@ -260,10 +260,9 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->ref = h->ws + L.off_ref;
   h->refspec = reinterpret_cast<float2*>(h->ws + L.off_refspec);
   h->fscale = reinterpret_cast<float4*>(h->ws + L.off_fscale);
-  const size_t nseg = L.seg_bin.size();
-  h->seg_bin = reinterpret_cast<int32_t*>(h->ws + L.off_segs);
-  h->seg_row0 = h->seg_bin + nseg;
-  h->bin_seg0 = h->seg_row0 + nseg;
+  h->seg_first = reinterpret_cast<int32_t*>(h->ws + L.off_segs);
+  h->bin_seg0 = h->seg_first + L.seg_first.size();
+  h->bin_slots = reinterpret_cast<int32_t*>(h->ws + L.off_bin_slots);
   h->part = reinterpret_cast<double*>(h->ws + L.off_part);
   h->part_cnt = reinterpret_cast<long long*>(h->ws + L.off_part_cnt);
   if (L.backward) {
@@ -293,11 +292,11 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
     e = hipMemcpyAsync(h->lags, L.lags.data(), L.lags.size() * 4, hipMemcpyHostToDevice,
                        h->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h->seg_bin, L.seg_bin.data(), nseg * 4, hipMemcpyHostToDevice,
-                       h->stream);
+    e = hipMemcpyAsync(h->seg_first, L.seg_first.data(), L.seg_first.size() * 4,
+                       hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(h->seg_row0, L.seg_row0.data(), nseg * 4, hipMemcpyHostToDevice,
-                       h->stream);
+    e = hipMemcpyAsync(h->bin_slots, L.bin_slots.data(), L.bin_slots.size() * 4,
+                       hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->bin_seg0, L.bin_seg0.data(), L.bin_seg0.size() * 4,
                        hipMemcpyHostToDevice, h->stream);
@@ -462,8 +461,8 @@ nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
   nfs_status st = finish_sums(h);
   if (st != NFS_OK) return st;
   const nfs::Layout& L = h->L;
-  hipError_t e = nfs::launch_bins(L.n, L.n_bins, h->acc, L.n_lags, h->tiles, h->seg_bin,
-                                  h->seg_row0, int(L.seg_bin.size()), h->bin_seg0, h->part,
+  hipError_t e = nfs::launch_bins(L.n_bins, h->acc, L.n_lags, h->bin_slots, h->seg_first,
+                                  int(L.seg_first.size() - 1), h->bin_seg0, h->part,
                                   h->part_cnt, h->lags, h->t_pushed, h->status, D, bin_counts,
                                   lag_pairs, status, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "bin kernel launch");

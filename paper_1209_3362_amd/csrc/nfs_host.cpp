@@ -117,17 +117,46 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.slots = base;
   o.mode_stride = int64_t(align_up(size_t(base), 64));
 
-  // Binning segments, rings in order, kSegRows ring rows each.
+  // Binning table and segments, rings in order. On row k_y the half-plane
+  // modes of ring b are the run k_x in [ceil_sqrt(lo - k_y^2),
+  // ceil_sqrt(hi - k_y^2)); every one of them is stored (|k| < n/2).
+  o.bin_slots.reserve(size_t(o.modes));
   o.bin_seg0.push_back(0);
   for (int b = 0; b < o.n_bins; ++b) {
     int64_t lo, hi;
     ring_bounds(o.n, o.n_bins, b, &lo, &hi);
     const int R = int(isqrt_u64(uint64_t(hi - 1)));
-    for (int ky = -R; ky <= R; ky += kSegRows) {
-      o.seg_bin.push_back(b);
-      o.seg_row0.push_back(ky);
+    const int32_t first = int32_t(o.bin_slots.size());
+    for (int ky = -R; ky <= R; ++ky) {
+      const int64_t ky2 = int64_t(ky) * ky;
+      const int a = lo - ky2 > 0 ? int(ceil_sqrt_i64(lo - ky2)) : 0;
+      const int e = int(ceil_sqrt_i64(hi - ky2));
+      const int r = ky >= 0 ? ky : ky + o.n;
+      for (int kx = a; kx < e; ++kx)
+        o.bin_slots.push_back(2 * ring_slot_host(o, r, kx) + (kx > 0 ? 1 : 0));
     }
-    o.bin_seg0.push_back(int32_t(o.seg_bin.size()));
+    const int32_t last = int32_t(o.bin_slots.size());
+    int32_t s = first;
+    do {
+      o.seg_first.push_back(s);
+      s += kSegModes;
+    } while (s < last);
+    o.bin_seg0.push_back(int32_t(o.seg_first.size()));
+  }
+  o.seg_first.push_back(int32_t(o.bin_slots.size()));
+  // The rings partition the stored modes: each is listed exactly once.
+  {
+    std::vector<char> seen(size_t(o.slots), 0);
+    bool ok = int64_t(o.bin_slots.size()) == o.modes;
+    for (size_t i = 0; ok && i < o.bin_slots.size(); ++i) {
+      const int32_t slot = o.bin_slots[i] >> 1;
+      ok = slot >= 0 && slot < o.slots && !seen[size_t(slot)];
+      if (ok) seen[size_t(slot)] = 1;
+    }
+    if (!ok) {
+      if (err) *err = "binning table does not list every stored mode once";
+      return NFS_E_ARG;
+    }
   }
 
   const int max_group = kMaxLagsPerWave * kMaxPairWaves;
@@ -158,8 +187,9 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   // Row sums of |frame - reference|, for the FP16 scale only.
   o.off_rowabs = take(o.spec_dtype == NFS_SPEC_F16 ? size_t(o.batch) * o.n * 8 : 0);
   o.off_acc = take(size_t(o.n_lags) * o.mode_stride * 4);
-  const size_t nseg = o.seg_bin.size();
-  o.off_segs = take((2 * nseg + o.bin_seg0.size()) * 4);
+  const size_t nseg = o.seg_first.size() - 1;
+  o.off_segs = take((o.seg_first.size() + o.bin_seg0.size()) * 4);
+  o.off_bin_slots = take(o.bin_slots.size() * 4);
   o.off_part = take(nseg * o.n_lags * 8);
   o.off_part_cnt = take(nseg * 8);
   o.off_status = take(kAlign);

@@ -16,8 +16,8 @@ namespace nfs {
 constexpr int kMinN = 16;
 constexpr int kMaxN = 4096;
 constexpr size_t kAlign = 256;
-// Ring rows summed by one workgroup of the binning pass.
-constexpr int kSegRows = 64;
+// Stored modes summed by one workgroup of the binning pass.
+constexpr int kSegModes = 256;
 // Target size of the row-transform intermediate of one batch of frames.
 constexpr size_t kBatchBytes = size_t(128) << 20;
 constexpr int kMaxBatch = 1024;
@@ -59,10 +59,13 @@ struct Layout {
   // T = n / 16 tiles of 8 columns.
   std::vector<int32_t> tiles;
   std::vector<LagGroup> groups;
-  // Binning segments: segment s covers rows k_y in [seg_row0[s],
-  // seg_row0[s] + kSegRows) of ring seg_bin[s]; ring b owns segments
-  // [bin_seg0[b], bin_seg0[b + 1]).
-  std::vector<int32_t> seg_bin, seg_row0, bin_seg0;
+  // Binning table: the stored modes of ring 0, then of ring 1, ..., each as
+  // 2 * slot + (k_x > 0), rows k_y ascending and k_x ascending within a row
+  // (weight 2 for k_x > 0: the mode and its mirror -k; 1 on k_x = 0, where
+  // both are stored). Segment s covers entries [seg_first[s],
+  // seg_first[s + 1]) (at most kSegModes, of one ring; every ring has at
+  // least one segment); ring b owns segments [bin_seg0[b], bin_seg0[b + 1]).
+  std::vector<int32_t> bin_slots, seg_first, bin_seg0;
   // Byte offsets into the workspace.
   size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_rowabs = 0, off_acc = 0;
   size_t off_status = 0, off_tw = 0, off_width = 0, off_tiles = 0;
@@ -78,7 +81,7 @@ struct Layout {
   std::vector<int32_t> mode_bin;   // [mode_stride], 0 past the stored modes
   std::vector<int64_t> bin_count;  // [n_bins]
   size_t off_fscale = 0;  // after the ring: kScaleBytes per slot
-  size_t off_segs = 0, off_part = 0, off_part_cnt = 0;
+  size_t off_segs = 0, off_bin_slots = 0, off_part = 0, off_part_cnt = 0;
   size_t off_lags = 0, total = 0;
 };
 

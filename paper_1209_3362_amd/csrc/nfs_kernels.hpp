@@ -59,15 +59,14 @@ hipError_t launch_pairs(const void* ring, int spec, bool kahan, const float2* re
                         int modes, int hist, int waves, int per_wave, size_t lds,
                         hipStream_t s);
 
-// Azimuthal binning from the sums acc [slots][n_lags] (mode-major, tiled
-// slot layout: tiles, see ring_slot): segment
-// partials (segments seg_bin / seg_row0 of kSegRows ring rows), then per
-// ring D[l][b] = sum_{k in ring b} w(k) acc[k][l] / (C_b * pairs_l) in
-// double, counts[b] = C_b, pairs[l] = max(0, N - lag_l), status_out[0]
+// Azimuthal binning from the sums acc [slots][n_lags] (mode-major): segment
+// partials over the binning table bin_slots (entries 2 * slot + (k_x > 0),
+// ring by ring; segment s covers entries [seg_first[s], seg_first[s + 1])),
+// then per ring D[l][b] = sum_{k in ring b} w(k) acc[k][l] / (C_b * pairs_l)
+// in double, counts[b] = C_b, pairs[l] = max(0, N - lag_l), status_out[0]
 // from *status. pairs_l == 0 gives NaN.
-hipError_t launch_bins(int n, int n_bins, const float* acc, int n_lags,
-                       const int32_t* tiles, const int32_t* seg_bin,
-                       const int32_t* seg_row0, int n_segs, const int32_t* bin_seg0,
+hipError_t launch_bins(int n_bins, const float* acc, int n_lags, const int32_t* bin_slots,
+                       const int32_t* seg_first, int n_segs, const int32_t* bin_seg0,
                        double* part, long long* part_cnt, const int32_t* lags,
                        int64_t n_frames, const int32_t* status, double* D, int64_t* counts,
                        int64_t* pairs, int32_t* status_out, hipStream_t s);

@@ -79,6 +79,14 @@ def code(**kw):
     return "NFS_OK"
 
 
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024, 2048, 4096])
+def test_binning_table_covers_every_stored_mode(n):
+    """Planning lists, ring by ring, every stored mode exactly once (the plan
+    is refused otherwise) for every frame size and several ring counts."""
+    for nb in sorted({1, 3, max(1, n // 8), n // 4, n // 2 - 1, n // 2} - {0}):
+        assert code(n=n, n_bins=nb, lags=[1], capacity=4) == "NFS_OK", (n, nb)
+
+
 def test_descriptor_validation():
     assert code() == "NFS_OK"
     assert code(n=100) == "NFS_E_SIZE"
