@@ -299,16 +299,21 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
         }
       }
     };
+    // Older rows are read only for lag slots with some target that has a
+    // partner in this chunk (the same wave-uniform test sum_slot makes).
+    auto wanted = [&](int s) { return s < l_count && c + S > first[s]; };
     float2 o0[RPT], o1[RPT];
-    load_rows(o0, rows(tau[0]));
+    if (wanted(0)) load_rows(o0, rows(tau[0]));
     dev::static_for<MAXLW>([&](auto SS) {
       constexpr int s = decltype(SS)::value;
       constexpr int nx = s + 1 < MAXLW ? s + 1 : s;
       if constexpr ((s & 1) == 0) {
-        if constexpr (s + 1 < MAXLW) load_rows(o1, rows(tau[nx]));
+        if constexpr (s + 1 < MAXLW)
+          if (wanted(nx)) load_rows(o1, rows(tau[nx]));
         sum_slot(o0, s);
       } else {
-        if constexpr (s + 1 < MAXLW) load_rows(o0, rows(tau[nx]));
+        if constexpr (s + 1 < MAXLW)
+          if (wanted(nx)) load_rows(o0, rows(tau[nx]));
         sum_slot(o1, s);
       }
     });
