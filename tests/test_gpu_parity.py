@@ -165,6 +165,38 @@ def test_run_twice_is_bitwise_identical():
     assert np.array_equal(a[0], b[0])
 
 
+def test_reset_reuses_a_plan_exactly():
+    """After nfs_reset the first pair launch stores its sums instead of
+    adding them: a reused plan gives bit for bit what a fresh plan gives,
+    windowed rings included, and a reset plan read before any push gives
+    no pairs (D NaN) with the ring counts unchanged."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfg = gen.config("c1", n=64, N=60, n_bins=32)
+    lags = [1, 3, 7, 20]
+    say("reset: 60 frames 64x64 f32, reuse after reset, capacities 60 and 30, seeds 11/12")
+    a = gen.make_stack(cfg, 11).cuda()
+    b = gen.make_stack(cfg, 12).cuda()
+    for cap in (60, 30):
+        fresh = nfs.Plan(64, lags, 32, in_dtype="f32", capacity=cap)
+        fresh.push(b)
+        want = [x.cpu().numpy() for x in fresh.structure_function()]
+        fresh.close()
+        plan = nfs.Plan(64, lags, 32, in_dtype="f32", capacity=cap)
+        plan.push(a)
+        plan.structure_function()
+        plan.reset()
+        plan.push(b)
+        got = [x.cpu().numpy() for x in plan.structure_function()]
+        for x, y in zip(got, want):
+            assert np.array_equal(x, y, equal_nan=True), cap
+        plan.reset()
+        D, C, P, st = [x.cpu().numpy() for x in plan.structure_function()]
+        assert np.all(np.isnan(D)) and np.all(P == 0) and int(st.reshape(-1)[0]) == 0
+        assert np.array_equal(C, want[1])
+        plan.close()
+
+
 def test_edge_lags_and_tiny_stacks():
     cfg = gen.config("c1", n=32, N=9, n_bins=16)
     say("edge lags: lag 0, lags >= N, N = 9 and N = 1")
