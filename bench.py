@@ -345,7 +345,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU per process; --gpus must be 1 (multi-GPU sharding is a design only)"}))
         sys.exit(2)
 
     import torch
