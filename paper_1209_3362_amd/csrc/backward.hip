@@ -373,15 +373,19 @@ hipError_t inverse_2d(int in_dtype, const float2* gk, int64_t mode_stride,
                       int nframes, float2* z, float* gprime, const void* frames,
                       const float* window, double2* rowsums, hipStream_t s) {
   using C = ColCfg<N>;
-  // About 2048 workgroups (several per CU at once, two rounds), at least one
-  // and at most 8 frames each.
-  auto per = [&](int groups) { return std::max(1, std::min(8, nframes * groups / 2048)); };
-  const int pc = per(C::GROUPS);
+  // At least one and at most 8 frames per workgroup, for about `target`
+  // workgroups: 1024 for the column transform (its set-up is amortised over
+  // more frames; measured faster than 2048 and 512), 2048 for the row
+  // transform (measured faster than 1024).
+  auto per = [&](int groups, int target) {
+    return std::max(1, std::min(8, nframes * groups / target));
+  };
+  const int pc = per(C::GROUPS, 1024);
   const unsigned col_blocks = unsigned(C::GROUPS * ((nframes + pc - 1) / pc));
   hipLaunchKernelGGL(inv_col_kernel<N>, dim3(col_blocks), dim3(C::THREADS), 0, s, gk,
                      mode_stride, row_width, tiles, tw, nframes, pc, z);
   constexpr int RG = N / C::CW;
-  const int pr = per(RG);
+  const int pr = per(RG, 2048);
   const dim3 grid(unsigned(RG * ((nframes + pr - 1) / pr)));
 #define NFS_INVROW_GO(T, W)                                                                   \
   hipLaunchKernelGGL((inv_row_kernel<N, T, W>), grid, dim3(C::THREADS), 0, s, z, gprime,     \
