@@ -417,7 +417,8 @@ hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
                                int64_t n_frames, int64_t t0, int nframes, float2* gk,
                                hipStream_t s) {
   // The windowed kernel when a window of kFB targets plus the lags either
-  // side fits 64 KB of LDS with 32, 16 or 8 slots per workgroup.
+  // side fits 64 KB of LDS with 16 or 8 slots per workgroup (16 measured
+  // faster than 32, which holds half as many workgroups per CU, and than 8).
   const int64_t rows = kFB + 2 * int64_t(max_lag);
   const int fblocks = (nframes + kFB - 1) / kFB;
   const char* rr = static_cast<const char*>(ring);
@@ -434,7 +435,6 @@ hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
     else NFS_GRADW_GO(kSpecF16, KMV);                                                         \
     return hipGetLastError();                                                                 \
   }
-  NFS_GRADW_KM(32)
   NFS_GRADW_KM(16)
   NFS_GRADW_KM(8)
 #undef NFS_GRADW_KM
