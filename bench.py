@@ -28,11 +28,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "frame-pairs/sec and HBM GB/s for D(q,tau), 1024^2 x 1000 frames, 1 GPU"
-# MI355X published peaks and the non-packed FP32 VALU rate derived from the
-# unit counts: 256 CUs x 64 lanes x 2.4 GHz lane-instructions per second.
+# MI355X published peaks: HBM3E 8 TB/s, FP32 vector 157.3 TFLOP/s (packed
+# FP32 FMAs). The library's device code is built without packed FP32
+# instructions, so the rate it can reach is the non-packed one derived from
+# the unit counts: 256 CUs x 64 lanes x 2.4 GHz lane-instructions per
+# second, 78.6 TFLOP/s counting an FMA as 2 FLOP.
 HBM_PEAK_GBPS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
 VALU_LANE_OPS = 256 * 64 * 2.4e9
-FP32_FMA_PEAK_TFLOPS = VALU_LANE_OPS * 2 / 1e12  # 78.6
+FP32_NONPACKED_TFLOPS = VALU_LANE_OPS * 2 / 1e12  # 78.6
 
 
 METRIC_C3 = "frame-pairs/sec for D(q,tau), 1024^2 x 4000 frames, lags 1..400, 1 GPU"
@@ -48,35 +52,36 @@ WORKLOADS = {
 METRIC_C4 = ("frame-pairs/sec for D(q,tau) over 16 sequences of uneven frame size and length "
              "(batching form), 1 GPU")
 
+# Counter summaries (profiles/): each names the sources that shape its
+# kernel's memory traffic and their sha256; a figure is reported only while
+# those sources are unchanged.
 PAIR_COUNTERS = os.path.join(ROOT, "profiles", "pair_kernel_1000x1024_counters.md")
-# What shapes the pair kernel's memory traffic: the kernel, its device
-# helpers and its launch planner.
-PAIR_SOURCES = ["paper_1209_3362_amd/csrc/pairs.hip", "paper_1209_3362_amd/csrc/nfs_device.hpp",
-                "paper_1209_3362_amd/csrc/pair_plan.hpp", "paper_1209_3362_amd/csrc/pair_plan.cpp"]
+TRANSFORM_COUNTERS = os.path.join(ROOT, "profiles", "transform_1000x1024_counters.md")
 
 
-def pair_source_digest():
+def source_digest(rels):
     import hashlib
     h = hashlib.sha256()
-    for rel in PAIR_SOURCES:
+    for rel in rels:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def pair_traffic():
-    """HBM bytes per pair-kernel launch from the committed counter summary,
-    or None when it is missing or the kernel's sources changed since."""
+def counter_figure(path, key):
+    """Field `key` of a counter summary, or None when the summary is missing
+    or the sources it lists changed since the counters were taken."""
     try:
         fields = {}
-        with open(PAIR_COUNTERS) as f:
+        with open(path) as f:
             for line in f:
                 if ":" in line and line.startswith("- "):
                     k, v = line[2:].split(":", 1)
                     fields[k.strip()] = v.strip().strip("`")
-        if fields.get("source_sha256") != pair_source_digest():
+        rels = [r.strip() for r in fields["sources"].split(",")]
+        if fields.get("source_sha256") != source_digest(rels):
             return None
-        return float(fields["traffic_bytes_per_launch"])
+        return float(fields[key])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -88,10 +93,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-frames", type=int, default=80)
+    ap.add_argument("--cpu-frames", type=int, default=160)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer 5 times (known bytes), to scale "
                          "memory counters of the same profiler run")
+    ap.add_argument("--bandwidth-probe", action="store_true",
+                    help="only measure copy/read/write rates of cache-resident and "
+                         "HBM-sized buffers with the library's probe kernel")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--batch-streams", type=int, default=0,
                     help="c4: time only an eager run on this many streams (for profiling)")
@@ -120,20 +128,67 @@ def frame_pairs(N, lags):
     return sum(max(0, N - t) for t in lags)
 
 
+def host_cores():
+    """Host threads for the CPU baseline: the cores this process may run on,
+    at most 16 (the CPU share of one GPU on the benchmark machines)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(frames_gpu, cfg, n_frames):
-    """Time the FP64 oracle on the first `n_frames` frames, lags < n_frames."""
+    """Time the FP64 oracle on the first `n_frames` frames and the lags below
+    n_frames, on every host core this process gets: the oracle's own
+    functions, unchanged, called from a thread pool over frames (O1-O3:
+    normalise, full-plane transform) and over blocks of k-rows (O4: pair
+    loop), then its binning (O5-O6). NumPy releases the interpreter lock in
+    its transforms and array arithmetic, so the threads run in parallel."""
     import numpy as np
     import oracle
+    from concurrent.futures import ThreadPoolExecutor
     lags = [t for t in cfg["lags"] if t < n_frames]
-    sample = frames_gpu[:n_frames].cpu().numpy().astype(np.float64)
+    n, nb = cfg["n"], cfg["n_bins"]
+    sample = frames_gpu[:n_frames].cpu().numpy()
+    cores = host_cores()
     t0 = time.perf_counter()
-    oracle.structure_function(sample, lags, cfg["n_bins"])
+    spec = np.empty((n_frames, n, n), dtype=np.complex128)
+
+    def transform(t):
+        spec[t] = oracle.spectra(oracle.normalise(sample[t:t + 1])[0])[0]
+
+    P = np.empty((len(lags), n, n), dtype=np.float64)
+    rows = max(1, n // (4 * cores))
+
+    def pairs(r0):
+        P[:, r0:r0 + rows] = oracle.pair_power(spec[:, r0:r0 + rows], lags)[0]
+
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(transform, range(n_frames)))
+        list(ex.map(pairs, range(0, n, rows)))
+    bidx = oracle.bin_index(n, nb)
+    D = oracle.azimuthal_average(P, bidx, nb)
     dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(D))
     fp = frame_pairs(n_frames, lags)
-    return {"value": fp / dt, "unit": "frame-pairs/s", "cores": 1, "kind": "oracle",
+    return {"value": fp / dt, "unit": "frame-pairs/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
             "sample": (f"first {n_frames} frames of the timed stack, the {len(lags)} of its "
-                       f"lags below {n_frames} ({fp} frame-pairs), 512 rings, FP64 NumPy "
-                       f"full-plane oracle, {dt:.1f} s on one host thread")}
+                       f"lags below {n_frames} ({fp} frame-pairs), {nb} rings: FP64 NumPy "
+                       f"full-plane oracle (its functions unchanged) on {cores} threads over "
+                       f"frames and k-row blocks, {dt:.1f} s")}
 
 
 def copy_calibration():
@@ -148,6 +203,38 @@ def copy_calibration():
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read_per_launch": n, "copy_bytes_written_per_launch": n,
                       "launches": 5}))
+
+
+def bandwidth_probe(args):
+    """Copy, read and write rates of the library's probe kernel over buffers
+    that fit the 256 MB Infinity Cache (16..128 MiB) and over ones that do
+    not (1 and 4 GiB): separates the cache-resident rate from the HBM rate.
+    Each size and mode: 5 warm-up passes, then the median of 20 event-timed
+    passes."""
+    import statistics
+    import torch
+    import paper_1209_3362_amd as nfs
+    out = {}
+    for mib in (16, 32, 64, 128, 1024, 4096):
+        nbytes = mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for mode, name in ((0, "copy"), (1, "read"), (2, "write")):
+            for _ in range(5):
+                nfs.probe_bandwidth(mode, src, dst, nbytes)
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(20)]
+            for a, b in evs:
+                a.record()
+                nfs.probe_bandwidth(mode, src, dst, nbytes)
+                b.record()
+            torch.cuda.synchronize()
+            ms = statistics.median(a.elapsed_time(b) for a, b in evs)
+            moved = 2 * nbytes if mode == 0 else nbytes
+            out[f"{name}_{mib}MiB_gbps"] = moved / (ms * 1e-3) / 1e9
+        del src, dst
+        torch.cuda.empty_cache()
+    print(json.dumps({"bandwidth_probe": out}))
 
 
 def host_ingest(args, cfg, frames):
@@ -344,6 +431,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.bandwidth_probe:
+        bandwidth_probe(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs on one GPU per process; --gpus must be 1 (multi-GPU sharding is a design only)"}))
         sys.exit(2)
@@ -416,10 +506,16 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    ms_fft = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    ms_pair = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
-    ms_bin = sum(e[2].elapsed_time(e[3]) for e in evs) / args.steps
-    ms_step = wall * 1e3 / args.steps
+    import statistics
+    med = statistics.median
+    # Per step, HIP events on the plan's stream: the whole step and its
+    # stages; the step time is the median over the timed steps.
+    ms_steps = [e[0].elapsed_time(e[3]) for e in evs]
+    ms_fft = med([e[0].elapsed_time(e[1]) for e in evs])
+    ms_pair = med([e[1].elapsed_time(e[2]) for e in evs])
+    ms_bin = med([e[2].elapsed_time(e[3]) for e in evs])
+    ms_step = med(ms_steps)
+    ms_wall = wall * 1e3 / args.steps
 
     D = out[0].cpu()
     assert bool(torch.isfinite(D).all()), "non-finite D"
@@ -453,6 +549,13 @@ def main():
     # Pair kernel: per pair and mode 2 subtractions + 2 FMAs = 6 FLOP
     # (4 VALU lane-instructions; the Kahan form adds a few per chunk).
     pair_tflops = 6.0 * pair_k / (ms_pair * 1e-3) / 1e12
+    base = (args.workload, args.spec, args.accum, args.capacity or N) == ("c2", "f32", "plain", N)
+    # Transform stage (A1-A3): algorithmic bytes are the frames read once and
+    # the stored modes written once; the row-to-column intermediate is not
+    # algorithmic. Its counter traffic (all row and column passes of one
+    # step) comes from the committed summary.
+    tr_bytes = bytes_frames + bytes_spec
+    tr_gbps = tr_bytes / (ms_fft * 1e-3) / 1e9
 
     rec = {
         "metric": METRIC if args.workload == "c2" else METRIC_C3,
@@ -462,6 +565,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_stat": "median of per-step HIP-event times",
+        "ms_per_step_mean_wall": ms_wall,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -483,12 +588,26 @@ def main():
             "kernel": "pair_kernel (lag-pair accumulator)",
             "bound": "alu",
             "achieved": pair_tflops,
-            "peak": FP32_FMA_PEAK_TFLOPS,
+            "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": pair_tflops / FP32_FMA_PEAK_TFLOPS,
-            "traffic": pair_traffic() if (args.workload, args.spec, args.accum) ==
-                       ("c2", "f32", "plain") else None,
+            "frac": pair_tflops / FP32_PEAK_TFLOPS,
+            "traffic": counter_figure(PAIR_COUNTERS, "traffic_bytes_per_launch") if base
+                       else None,
+            "flop_per_launch": 6.0 * pair_k,
+            "peak_nonpacked": FP32_NONPACKED_TFLOPS,
+            "frac_nonpacked": pair_tflops / FP32_NONPACKED_TFLOPS,
             "valu_issue_frac": 4.0 * pair_k / (ms_pair * 1e-3) / VALU_LANE_OPS,
+        },
+        "transform_roofline": {
+            "kernel": "row_pass_kernel + col_pass_kernel (normalise, 2D transform, store)",
+            "bound": "hbm",
+            "achieved": tr_gbps,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": tr_gbps / HBM_PEAK_GBPS,
+            "algorithmic_bytes_per_step": tr_bytes,
+            "traffic": counter_figure(TRANSFORM_COUNTERS, "traffic_bytes_per_step") if base
+                       else None,
         },
     }
     if not args.no_cpu_baseline and args.workload == "c2":

@@ -315,6 +315,18 @@ const char* nfs_last_error(nfs_handle h);
  * modes that are not stored. Only frames still in the ring can be copied:
  * NFS_E_STATE otherwise. */
 nfs_status nfs_mode_count(nfs_handle h, int64_t* modes);
+
+/* Memory-bandwidth probe (measurement tool, no plan): one kernel over
+ * `bytes` bytes (a multiple of 16; src and dst 16-byte aligned device
+ * buffers) enqueued on `stream` (NULL = the default stream):
+ *   mode 0: copy src to dst (bytes read and bytes written);
+ *   mode 1: read src; dst receives 2048 checksum words (8 KB);
+ *   mode 2: write dst (src unused, may be NULL).
+ * Timing it over buffers that fit the 256 MB Infinity Cache and over larger
+ * ones separates the cache-resident rate from the HBM rate.
+ * NFS_E_ARG for a bad mode, size or pointer. */
+nfs_status nfs_probe_bandwidth(int32_t mode, const void* src, void* dst, size_t bytes,
+                               void* stream);
 nfs_status nfs_bin_map(nfs_handle h, int32_t* map);
 nfs_status nfs_copy_spectrum(nfs_handle h, int64_t t, float* out);
 

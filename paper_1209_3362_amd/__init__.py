@@ -6,7 +6,9 @@ this package only marshals arguments to it. Build it with
 GPU; every compute call does, and fails loudly when the library is missing.
 """
 from .nfs import (Plan, NfsError, load_library, library_path, status_name,
-                  workspace_size, structure_function, Batch, batch_capacities, STATUS)
+                  workspace_size, structure_function, Batch, batch_capacities, STATUS,
+                  probe_bandwidth)
 
 __all__ = ["Plan", "NfsError", "load_library", "library_path", "status_name",
-           "workspace_size", "structure_function", "Batch", "batch_capacities", "STATUS"]
+           "workspace_size", "structure_function", "Batch", "batch_capacities", "STATUS",
+           "probe_bandwidth"]

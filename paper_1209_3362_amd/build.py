@@ -45,7 +45,7 @@ def compile_cmds():
         # Packed FP32 instructions are switched off for all device code.
         cmds.append((obj, [hipcc(), "-x", "hip", "--offload-arch=" + ARCH,
                            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-                           "-ffp-contract=fast", "-munsafe-fp-atomics"] + common_flags()
+                           "-ffp-contract=fast"] + common_flags()
                      + ["-c", os.path.join(CSRC, src), "-o", obj]))
     for src in CPP_SOURCES:
         obj = os.path.join(BUILD, src + ".o")

@@ -86,6 +86,49 @@ __global__ void power_kernel(int n, int n_lags, const float* __restrict__ acc,
   }
 }
 
+// Memory-bandwidth probes over `vecs` 16-byte vectors: copy src to dst,
+// read src (a per-workgroup checksum goes to dst so the loads are kept), or
+// write dst. Grid-stride loops, four independent vectors in flight per
+// thread.
+template <int MODE>
+__global__ __launch_bounds__(256) void probe_kernel(const uint4* __restrict__ src,
+                                                    uint4* __restrict__ dst, size_t vecs) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  uint32_t x = 0;
+  for (; i + 3 * stride < vecs; i += 4 * stride) {
+    uint4 v[4];
+    if constexpr (MODE != 2) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = src[i + u * stride];
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = make_uint4(uint32_t(i + u), 1u, 2u, 3u);
+    }
+    if constexpr (MODE == 1) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) dst[i + u * stride] = v[u];
+    }
+  }
+  for (; i < vecs; i += stride) {
+    if constexpr (MODE == 0) dst[i] = src[i];
+    if constexpr (MODE == 1) x ^= src[i].x ^ src[i].y ^ src[i].z ^ src[i].w;
+    if constexpr (MODE == 2) dst[i] = make_uint4(uint32_t(i), 1u, 2u, 3u);
+  }
+  if constexpr (MODE == 1) {
+    __shared__ uint32_t red[4];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x ^= __shfl_xor(x, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      reinterpret_cast<uint32_t*>(dst)[blockIdx.x] = red[0] ^ red[1] ^ red[2] ^ red[3];
+  }
+}
+
 unsigned grid_for(int64_t items, int threads) {
   int64_t g = (items + threads - 1) / threads;
   if (g < 1) g = 1;
@@ -94,6 +137,23 @@ unsigned grid_for(int64_t items, int threads) {
 }
 
 }  // namespace
+
+hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const size_t vecs = bytes / 16;
+  // Eight workgroups of 256 threads per CU on 256 CUs.
+  const unsigned grid = 2048;
+  const uint4* a = static_cast<const uint4*>(src);
+  uint4* b = static_cast<uint4*>(dst);
+  if (mode == 0)
+    hipLaunchKernelGGL(probe_kernel<0>, dim3(grid), dim3(256), 0, s, a, b, vecs);
+  else if (mode == 1)
+    hipLaunchKernelGGL(probe_kernel<1>, dim3(grid), dim3(256), 0, s, a, b, vecs);
+  else if (mode == 2)
+    hipLaunchKernelGGL(probe_kernel<2>, dim3(grid), dim3(256), 0, s, a, b, vecs);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 hipError_t launch_fill_u32(void* dst, size_t words, uint32_t value, hipStream_t s) {
   if (words == 0) return hipSuccess;

@@ -551,6 +551,17 @@ nfs_status nfs_bin_map(nfs_handle h, int32_t* map) {
   return NFS_OK;
 }
 
+nfs_status nfs_probe_bandwidth(int32_t mode, const void* src, void* dst, size_t bytes,
+                               void* stream) {
+  if (mode < 0 || mode > 2 || bytes == 0 || bytes % 16 != 0) return NFS_E_ARG;
+  if ((mode != 2 && !src) || !dst) return NFS_E_ARG;
+  if ((mode != 2 && reinterpret_cast<uintptr_t>(src) % 16) ||
+      reinterpret_cast<uintptr_t>(dst) % 16)
+    return NFS_E_ARG;
+  hipError_t e = nfs::launch_probe(mode, src, dst, bytes, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? NFS_OK : NFS_E_HIP;
+}
+
 nfs_status nfs_copy_spectrum(nfs_handle h, int64_t t, float* out) {
   if (!is_live(h)) return NFS_E_STATE;
   if (!out) return fail(h, NFS_E_ARG, "out is NULL");

@@ -71,6 +71,11 @@ hipError_t launch_bins(int n_bins, const float* acc, int n_lags, const int32_t* 
                        int64_t n_frames, const int32_t* status, double* D, int64_t* counts,
                        int64_t* pairs, int32_t* status_out, hipStream_t s);
 
+// Bandwidth probe over `bytes` (a multiple of 16): mode 0 copies src to
+// dst, 1 reads src (dst receives one checksum word per workgroup, 2048
+// words), 2 writes dst.
+hipError_t launch_probe(int mode, const void* src, void* dst, size_t bytes, hipStream_t s);
+
 // Fills `words` 32-bit words at dst with `value`.
 hipError_t launch_fill_u32(void* dst, size_t words, uint32_t value, hipStream_t s);
 

@@ -84,6 +84,7 @@ def load_library():
         "nfs_copy_spectrum": (i32, [P, i64, P]),
         "nfs_power_spectra_2d": (i32, [P, P]),
         "nfs_backward": (i32, [P, P, P, P, P]),
+        "nfs_probe_bandwidth": (i32, [i32, P, P, sz, P]),
         "nfs_batch_workspace_size": (i32, [ctypes.POINTER(NfsDesc), i32, ctypes.POINTER(sz),
                                            ctypes.POINTER(sz)]),
         "nfs_batch_capacities": (i32, [ctypes.POINTER(NfsDesc), ctypes.POINTER(i64), i32, sz,
@@ -135,6 +136,16 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def check_backward_frames(pushed, n, shape):
+    """nfs_backward reads N frames and writes N frame gradients, N the number
+    of frames pushed: the stack handed to it must be exactly [N][n][n]."""
+    if pushed < 1:
+        raise ValueError("no frame pushed: nothing to differentiate")
+    if tuple(shape) != (pushed, n, n):
+        raise ValueError(f"frames must be the {pushed} pushed frames, [{pushed}][{n}][{n}]; "
+                         f"got {list(shape)}")
+
+
 class Plan:
     """A structure-function plan on one GPU.
 
@@ -170,6 +181,7 @@ class Plan:
         self.stream = stream or torch.cuda.current_stream(self.device)
         self.host_staging = bool(host_staging)
         self._borrowed = []  # host frames the copy stream may still read
+        self.pushed = 0      # frames pushed since the plan was made or reset
         d, self._lags_keep = _desc(self.n, self.lags, self.n_bins, in_dtype, capacity, wptr,
                                    spec, accum, self.host_staging, backward)
         size = ctypes.c_size_t(0)
@@ -217,6 +229,7 @@ class Plan:
         else:
             self._check(self.lib.nfs_push_frames(self.handle, _ptr(frames),
                                                  ctypes.c_int64(frames.shape[0])))
+        self.pushed += int(frames.shape[0])
         return self
 
     def synchronize(self):
@@ -275,6 +288,7 @@ class Plan:
             raise ValueError("dL_dD must be [n_lags][n_bins]")
         if frames.device != self.device or frames.dtype != self.torch_dtype:
             raise ValueError(f"frames must be {self.torch_dtype} on {self.device}")
+        check_backward_frames(self.pushed, self.n, tuple(frames.shape))
         frames = frames.contiguous()
         gf = torch.empty(frames.shape, dtype=torch.float32, device=self.device) \
             if frames_grad else None
@@ -301,6 +315,7 @@ class Plan:
 
     def reset(self):
         self._check(self.lib.nfs_reset(self.handle))
+        self.pushed = 0
 
     def close(self):
         if getattr(self, "handle", None):
@@ -353,6 +368,18 @@ def structure_function(frames, lags, n_bins, window=None, spec="f32", accum="pla
     with respect to float32 frames and the window (torch autograd)."""
     return _StructureFunction.apply(frames, window, [int(t) for t in lags], int(n_bins), spec,
                                     accum)
+
+
+def probe_bandwidth(mode, src, dst, nbytes, stream=None):
+    """nfs_probe_bandwidth: enqueue one copy (0), read (1) or write (2) pass
+    over `nbytes` bytes of device tensors on `stream` (torch's current one by
+    default)."""
+    lib = load_library()
+    s = stream or torch.cuda.current_stream()
+    st = lib.nfs_probe_bandwidth(int(mode), None if src is None else _ptr(src), _ptr(dst),
+                                 ctypes.c_size_t(int(nbytes)), ctypes.c_void_p(s.cuda_stream))
+    if st != NFS_OK:
+        raise NfsError(st, lib.nfs_status_string(st).decode())
 
 
 def batch_capacities(seqs, budget):
@@ -439,10 +466,23 @@ class Batch:
         arrs = [(P * n_seq)(*[o[i].data_ptr() for o in outs]) for i in range(4)]
         return outs, (fr, cn, *arrs)
 
+    def _after_current(self):
+        """Order the batch's stream after the work already enqueued on the
+        current stream (which may still be producing the frames)."""
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+
+    def _before_current(self):
+        """Order later work on the current stream (reads of the outputs,
+        reuse of the frames' or outputs' memory) after the batch's run."""
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+
     def tune(self, frames_list):
         """Tune every sequence's pair-kernel launch shape on its frames
         (push, nfs_tune_pairs, reset per plan); returns the shapes."""
         self._arrays(frames_list)  # validates shapes and types
+        # The plans' pushes run on the batch's worker streams: let the
+        # frames be complete first.
+        torch.cuda.current_stream(self.device).synchronize()
         shapes = []
         for j, f in enumerate(frames_list):
             p = ctypes.c_void_p()
@@ -462,9 +502,11 @@ class Batch:
 
     def run(self, frames_list, sync=True):
         outs, args = self._arrays(frames_list)
+        self._after_current()
         st = self.lib.nfs_batch_run(self.handle, *args)
         if st != NFS_OK:
             raise NfsError(st, self.lib.nfs_status_string(st).decode())
+        self._before_current()
         if sync:
             self.stream.synchronize()
         return outs
@@ -473,6 +515,9 @@ class Batch:
         """Capture one run into a graph; returns the output tensors every
         replay rewrites."""
         outs, args = self._arrays(frames_list)
+        # Nothing is executed by the capture; replays order themselves after
+        # the current stream. Make the batch's stream idle before capturing.
+        self._after_current()
         self.stream.synchronize()
         st = self.lib.nfs_batch_capture(self.handle, *args)
         if st != NFS_OK:
@@ -481,9 +526,11 @@ class Batch:
         return outs
 
     def replay(self, sync=True):
+        self._after_current()
         st = self.lib.nfs_batch_replay(self.handle)
         if st != NFS_OK:
             raise NfsError(st, self.lib.nfs_status_string(st).decode())
+        self._before_current()
         if sync:
             self.stream.synchronize()
         return self._outs

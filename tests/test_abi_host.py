@@ -250,3 +250,14 @@ def test_calls_on_bad_handles_fail_cleanly():
     out = ctypes.c_void_p()
     assert lib.nfs_plan(None, None, 0, None, ctypes.byref(out)) == 1
     assert lib.nfs_plan(None, None, 0, None, None) == 1
+
+
+def test_backward_needs_exactly_the_pushed_frames():
+    """nfs_backward reads N frames and writes N frame gradients (N = frames
+    pushed), so the binding refuses any other stack shape before calling it."""
+    from paper_1209_3362_amd.nfs import check_backward_frames
+    check_backward_frames(5, 32, (5, 32, 32))
+    for pushed, shape in ((5, (4, 32, 32)), (5, (6, 32, 32)), (5, (5, 16, 32)),
+                          (0, (0, 32, 32)), (5, (5, 32))):
+        with pytest.raises(ValueError):
+            check_backward_frames(pushed, 32, shape)

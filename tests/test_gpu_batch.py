@@ -112,15 +112,94 @@ def test_batch_windowed_budget_matches_oracle():
         assert np.array_equal(g[1], ref["counts"]) and np.array_equal(g[2], ref["pairs"])
 
 
-def test_batch_workload_full_size_equals_single_plans():
+def test_batch_orders_after_the_current_stream():
+    """Frames still being written on the current stream when the batch is
+    run (no synchronisation in between) are read only once complete: the
+    batch's streams wait for the current stream, and the current stream
+    waits for the batch before the outputs are read."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfgs = _small_batch(count=4, seed=12)
+    say("batch ordering: 4 sequences, frames drawn and run without a synchronisation")
+    b = nfs.Batch([_seq(c) for c in cfgs], streams=3)
+    torch.cuda.synchronize()
+    frames = [gen.make_stack(c, c["seed"], device="cuda") for c in cfgs]
+    # more work on the current stream right before the run, touching the frames
+    for f in frames:
+        f.copy_(f.flip(0).flip(0))
+    got = _np(b.run(frames, sync=False))
+    b.close()
+    for c, f, g in zip(cfgs, frames, got):
+        want = _single(c, f)
+        for x, y in zip(g, want):
+            assert np.array_equal(x, y, equal_nan=True), c["name"]
+
+
+@pytest.fixture(scope="module")
+def c4_full():
+    """The 16-sequence batching workload (n 256..2048, 200..2000 frames, 32
+    log-spaced lags to N/2 each, master seed 4) drawn on the GPU once."""
+    require_gpu()
+    cfgs = gen.batch_workload(master_seed=4)
+    say("batch full size: 16 sequences drawn on the GPU (master seed 4)")
+    frames = [gen.make_stack(c, c["seed"], device="cuda") for c in cfgs]
+    torch.cuda.synchronize()
+    return cfgs, frames
+
+
+@pytest.fixture(scope="module")
+def c4_replayed(c4_full):
+    """The full workload captured once as a four-stream graph and replayed
+    twice, with eager work between the replays; both replays must agree bit
+    for bit. Returns the second replay's outputs on the host."""
+    import paper_1209_3362_amd as nfs
+    cfgs, frames = c4_full
+    say("batch full size: capture a four-stream graph, replay twice")
+    b = nfs.Batch([_seq(c) for c in cfgs], streams=4)
+    b.capture(frames)
+    first = _np(b.replay())
+    _ = (torch.randn(4096, device="cuda") ** 2).sum().item()
+    second = _np(b.replay())
+    b.close()
+    for x, y, c in zip(first, second, cfgs):
+        for u, v in zip(x, y):
+            assert np.array_equal(u, v, equal_nan=True), c["name"]
+    return second
+
+
+# every sequence of 2048^2 frames and the longest sequence (1926 frames of 512^2)
+C4_ORACLE_SEQS = [1, 4, 5, 15, 9]
+
+
+@pytest.mark.parametrize("j", C4_ORACLE_SEQS)
+def test_batch_workload_graph_replay_matches_oracle(c4_full, c4_replayed, j):
+    """Graph replays of the full batching workload against the FP64 oracle
+    on sampled rings (six per sequence, from the first to the last ring):
+    counts and pairs exact, D within 1e-4."""
+    import os
+    cfgs, frames = c4_full
+    c = cfgs[j]
+    nb = c["n_bins"]
+    bins = [1, 2, 7, nb // 8, nb // 2 - 1, nb - 1]
+    say(f"batch full size vs oracle: {c['name']} (n {c['n']}, {c['N']} frames), rings {bins}")
+    host = frames[j].cpu().numpy()
+    ref = oracle.structure_function_bins(host, c["lags"], nb, bins,
+                                         workers=min(16, os.cpu_count() or 1))
+    D, C, P, st = c4_replayed[j]
+    assert int(st.reshape(-1)[0]) == 0
+    assert np.array_equal(C[bins], ref["counts"]) and np.array_equal(P, ref["pairs"])
+    worst = assert_D_close(D[:, bins], ref["D"], rtol=1e-4)
+    print(f"{c['name']} replay vs oracle worst relative error {worst:.2e}")
+
+
+def test_batch_workload_full_size_equals_single_plans(c4_full):
     """The 16-sequence workload the benchmark times (n 256..2048, 200..2000
     frames, 32 lags each), run as one four-stream batch, equals single plans
     on the same frames bit for bit for every sequence."""
     import paper_1209_3362_amd as nfs
     require_gpu()
-    cfgs = gen.batch_workload(master_seed=4)
-    say("batch full size: 16 sequences drawn on the GPU (master seed 4), four streams")
-    frames = [gen.make_stack(c, c["seed"], device="cuda") for c in cfgs]
+    cfgs, frames = c4_full
+    say("batch full size: eager four-stream run")
     b = nfs.Batch([_seq(c) for c in cfgs], streams=4)
     got = _np(b.run(frames))
     b.close()

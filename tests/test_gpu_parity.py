@@ -221,7 +221,8 @@ def test_degenerate_frame_sets_status():
     assert st == NFS_E_DEGENERATE_FRAME
 
 
-@pytest.mark.parametrize("n,N", [(16, 12), (32, 10), (256, 8), (512, 6), (2048, 4), (4096, 3)])
+@pytest.mark.parametrize("n,N", [(16, 12), (32, 10), (256, 8), (512, 6), (1024, 6), (2048, 4),
+                                 (4096, 3)])
 def test_frame_sizes(n, N):
     cfg = gen.config("c1", n=n, N=N, n_bins=n // 2)
     lags = sorted({1, 2, N - 1})
@@ -247,7 +248,13 @@ def test_cosine_closed_form_on_gpu():
         for i, tau in enumerate(lags):
             want[i, b] += (eps * n * n) ** 2 * (1 - math.cos(om * tau)) / C[b]
     hit = want > 0
-    assert np.all(np.abs(D[hit] / want[hit] - 1) < 1e-3)
+    # The closed form holds for exact cosines; the frames are rounded to
+    # float32 (relative 6e-8 per pixel), which moves D by ~1e-7 relative,
+    # and the FP32 transform adds ~1e-7 per stored coefficient: the FP32
+    # bar of 1e-5 leaves two orders of margin.
+    rel = np.abs(D[hit] / want[hit] - 1)
+    print("cosine closed form worst relative error", rel.max())
+    assert np.all(rel < 1e-5)
     # off-mode bins hold only FP32 transform leakage
     assert np.all(np.abs(D[~hit]) < 1e-6 * want.max())
 
