@@ -62,7 +62,9 @@ typedef enum {
   NFS_E_STATE = 7,            /* handle destroyed or used out of order       */
   NFS_E_DEGENERATE_FRAME = 8, /* a frame had a non-positive spatial sum      */
   NFS_E_HIP = 9,              /* a HIP runtime call failed                   */
-  NFS_E_UNSUPPORTED = 10      /* option value not implemented                */
+  NFS_E_UNSUPPORTED = 10,     /* option value not implemented                */
+  NFS_E_SCRATCH = 11          /* problem larger than the static scratch of
+                                 nfs_structure_function_noalloc             */
 } nfs_status;
 
 /* Pixel type of the frames passed to nfs_push_frames. */
@@ -298,6 +300,39 @@ const char* nfs_status_string(nfs_status s);
 /* Description of the last error on this handle ("" if none); valid until
  * the next call on the handle. */
 const char* nfs_last_error(nfs_handle h);
+
+/* Allocation-free form, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the whole analysis of one stack in one call, with the plan's
+ * workspace taken from a device array inside the library instead of a
+ * caller-owned workspace. It plans `desc` (host_staging and backward must be
+ * 0, else NFS_E_ARG; capacity 0 = as many ring slots as the array holds),
+ * pushes `count` frames from device memory `frames` ([count][n][n] of the
+ * plan's pixel type, borrowed until `stream` passes the work), and writes
+ * D, bin_counts, lag_pairs and status exactly as nfs_structure_function
+ * does (same kernels, same results bit for bit as nfs_plan +
+ * nfs_push_frames + nfs_structure_function with the same desc); outputs are
+ * caller-owned device buffers. Calls no hipMalloc, hipFree or other
+ * device-allocating routine.
+ *
+ * The array holds NFS_STATIC_SCRATCH_BYTES bytes per GPU (allocated when
+ * the library's code is loaded on that GPU, kept until the process ends);
+ * a desc whose workspace (nfs_plan_workspace_size) exceeds it returns
+ * NFS_E_SCRATCH before any work is enqueued. The array is found for the
+ * current device (hipGetDevice); `stream` must belong to that device (NULL
+ * = its default stream), else NFS_E_ARG. Every call on a GPU uses that
+ * GPU's one array and it keeps the last call's contents: the call clears
+ * what must start at zero itself, and calls that overlap on one GPU (on
+ * different streams, or from several host threads) race and give wrong
+ * results. Work is enqueued on `stream`; the tables are uploaded with
+ * ordinary copies from host memory and the call waits once for them, as
+ * nfs_plan does. No handle outlives the call, so errors are reported by
+ * the status only. */
+#define NFS_STATIC_SCRATCH_BYTES (128u << 20)
+nfs_status nfs_structure_function_noalloc(const nfs_desc* desc, const void* frames,
+                                          int64_t count, double* D, int64_t* bin_counts,
+                                          int64_t* lag_pairs, int32_t* status, void* stream);
+
 
 /* Inspection entry points (tests and tools).
  *

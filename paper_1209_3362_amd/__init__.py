@@ -7,8 +7,8 @@ GPU; every compute call does, and fails loudly when the library is missing.
 """
 from .nfs import (Plan, NfsError, load_library, library_path, status_name,
                   workspace_size, structure_function, Batch, batch_capacities, STATUS,
-                  probe_bandwidth)
+                  probe_bandwidth, structure_function_noalloc)
 
 __all__ = ["Plan", "NfsError", "load_library", "library_path", "status_name",
            "workspace_size", "structure_function", "Batch", "batch_capacities", "STATUS",
-           "probe_bandwidth"]
+           "probe_bandwidth", "structure_function_noalloc"]

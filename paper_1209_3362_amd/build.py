@@ -17,7 +17,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnfs.so")
 
-HIP_SOURCES = ["fft.hip", "pairs.hip", "bins.hip", "misc.hip", "backward.hip"]
+HIP_SOURCES = ["fft.hip", "pairs.hip", "bins.hip", "misc.hip", "backward.hip",
+               "static_scratch.hip"]
 CPP_SOURCES = ["pair_plan.cpp", "nfs_host.cpp", "nfs_api.cpp", "nfs_batch.cpp"]
 ARCH = "gfx950"
 

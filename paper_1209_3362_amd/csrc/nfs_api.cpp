@@ -211,6 +211,8 @@ const char* nfs_status_string(nfs_status s) {
     case NFS_E_DEGENERATE_FRAME: return "a frame had a non-positive spatial sum";
     case NFS_E_HIP: return "HIP runtime error";
     case NFS_E_UNSUPPORTED: return "option not implemented";
+    case NFS_E_SCRATCH:
+      return "workspace larger than the library's static scratch (NFS_STATIC_SCRATCH_BYTES)";
   }
   return "unknown status";
 }
@@ -515,6 +517,40 @@ nfs_status nfs_backward(nfs_handle h, const double* dL_dD, const void* frames,
   if (e == hipSuccess && dL_dwindow) e = nfs::launch_window_out(L.n, h->gw, dL_dwindow, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "backward launch");
   return NFS_OK;
+}
+
+nfs_status nfs_structure_function_noalloc(const nfs_desc* desc, const void* frames,
+                                          int64_t count, double* D, int64_t* bin_counts,
+                                          int64_t* lag_pairs, int32_t* status, void* stream) {
+  if (!desc || !D || count < 0 || (count > 0 && !frames)) return NFS_E_ARG;
+  if (desc->host_staging || desc->backward) return NFS_E_ARG;
+  // Size check on the host, before anything touches the device: the layout
+  // the plan below will take (capacity 0 = derived from the array's size).
+  nfs::Layout L;
+  std::string err;
+  nfs_status st = nfs::make_layout(desc, NFS_STATIC_SCRATCH_BYTES, &L, &err);
+  if (st == NFS_E_WORKSPACE) return NFS_E_SCRATCH;
+  if (st != NFS_OK) return st;
+  if (L.total > NFS_STATIC_SCRATCH_BYTES) return NFS_E_SCRATCH;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return NFS_E_HIP;
+  if (stream) {
+    int sdev = -1;
+    if (hipStreamGetDevice(static_cast<hipStream_t>(stream), &sdev) != hipSuccess)
+      return NFS_E_HIP;
+    if (sdev != dev) return NFS_E_ARG;
+  }
+  void* ws = nullptr;
+  if (nfs::static_scratch(dev, &ws) != hipSuccess) return NFS_E_HIP;
+  nfs_handle h = nullptr;
+  st = nfs_plan(desc, ws, NFS_STATIC_SCRATCH_BYTES, stream, &h);
+  if (st != NFS_OK) return st;
+  st = nfs_push_frames(h, frames, count);
+  if (st == NFS_OK) st = nfs_structure_function(h, D, bin_counts, lag_pairs, status);
+  // The enqueued kernels take their arguments by value and the plan owns
+  // no stream or event, so the handle can go before the stream passes.
+  nfs_status st_destroy = nfs_destroy(h);
+  return st != NFS_OK ? st : st_destroy;
 }
 
 nfs_status nfs_reset(nfs_handle h) {

@@ -139,4 +139,8 @@ hipError_t launch_grad_finish(int n, int in_dtype, int nframes, const double2* r
 // out[p] = float(gw[p]) for the n x n pixels.
 hipError_t launch_window_out(int n, const double* gw, float* out, hipStream_t s);
 
+// Device address of the library's static scratch array (NFS_STATIC_SCRATCH_BYTES,
+// 256-byte aligned) on `device`, looked up once per device and cached.
+hipError_t static_scratch(int device, void** addr);
+
 }  // namespace nfs

@@ -15,6 +15,7 @@ STATUS = {
     0: "NFS_OK", 1: "NFS_E_ARG", 2: "NFS_E_SIZE", 3: "NFS_E_LAGS", 4: "NFS_E_BINS",
     5: "NFS_E_WORKSPACE", 6: "NFS_E_CAPACITY", 7: "NFS_E_STATE",
     8: "NFS_E_DEGENERATE_FRAME", 9: "NFS_E_HIP", 10: "NFS_E_UNSUPPORTED",
+    11: "NFS_E_SCRATCH",
 }
 IN_DTYPES = {"u16": 0, "f32": 1}
 SPEC_DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
@@ -85,6 +86,8 @@ def load_library():
         "nfs_power_spectra_2d": (i32, [P, P]),
         "nfs_backward": (i32, [P, P, P, P, P]),
         "nfs_probe_bandwidth": (i32, [i32, P, P, sz, P]),
+        "nfs_structure_function_noalloc": (i32, [ctypes.POINTER(NfsDesc), P, i64, P, P, P, P,
+                                                 P]),
         "nfs_batch_workspace_size": (i32, [ctypes.POINTER(NfsDesc), i32, ctypes.POINTER(sz),
                                            ctypes.POINTER(sz)]),
         "nfs_batch_capacities": (i32, [ctypes.POINTER(NfsDesc), ctypes.POINTER(i64), i32, sz,
@@ -134,6 +137,39 @@ def workspace_size(n, lags, n_bins, in_dtype="u16", capacity=0, window=False, sp
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def structure_function_noalloc(frames, lags, n_bins, in_dtype="u16", capacity=0,
+                                spec="f32", accum="plain", out=None, stream=None):
+    """nfs_structure_function_noalloc: D of one stack of device frames
+    [N][n][n] with the plan's workspace in the library's static device array
+    (no workspace argument). Outputs (D float64 [L][n_bins], counts int64
+    [n_bins], pairs int64 [L], status int32 [1]) are allocated here unless
+    `out` brings them; enqueued on `stream` (default: the current stream)."""
+    lib = load_library()
+    if frames.device.type != "cuda":
+        raise ValueError("frames must be on a GPU")
+    dtype = torch.uint16 if in_dtype == "u16" else torch.float32
+    if frames.dtype != dtype or frames.dim() != 3 or frames.shape[1] != frames.shape[2]:
+        raise ValueError(f"frames must be {dtype} [count][n][n]")
+    frames = frames.contiguous()
+    n = int(frames.shape[-1])
+    lags = [int(t) for t in lags]
+    if out is None:
+        out = (torch.empty((len(lags), int(n_bins)), dtype=torch.float64, device=frames.device),
+               torch.empty(int(n_bins), dtype=torch.int64, device=frames.device),
+               torch.empty(len(lags), dtype=torch.int64, device=frames.device),
+               torch.empty(1, dtype=torch.int32, device=frames.device))
+    D, counts, pairs, status = out
+    d, _keep = _desc(n, lags, n_bins, in_dtype, capacity, None, spec, accum)
+    stream = stream or torch.cuda.current_stream(frames.device)
+    with torch.cuda.device(frames.device):
+        st = lib.nfs_structure_function_noalloc(
+            ctypes.byref(d), _ptr(frames), ctypes.c_int64(frames.shape[0]), _ptr(D),
+            _ptr(counts), _ptr(pairs), _ptr(status), ctypes.c_void_p(stream.cuda_stream))
+    if st != NFS_OK:
+        raise NfsError(st, lib.nfs_status_string(st).decode())
+    return D, counts, pairs, status
 
 
 def check_backward_frames(pushed, n, shape):

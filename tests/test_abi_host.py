@@ -59,7 +59,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     lib = nfs.load_library()
-    for code in range(11):
+    for code in range(12):
         s = lib.nfs_status_string(code)
         assert s and s != b"unknown status"
     assert lib.nfs_status_string(99) == b"unknown status"
@@ -261,3 +261,40 @@ def test_backward_needs_exactly_the_pushed_frames():
                           (0, (0, 32, 32)), (5, (5, 32))):
         with pytest.raises(ValueError):
             check_backward_frames(pushed, 32, shape)
+
+
+def test_noalloc_checks_size_and_arguments_on_the_host():
+    """nfs_structure_function_noalloc validates the desc and rejects a plan
+    larger than the static scratch before touching the device (so these run
+    without a GPU)."""
+    lib = nfs.load_library()
+    limit = 128 << 20
+    # 1024^2 with a 100-slot ring needs far more than the static array.
+    d, _keep = nfs.nfs._desc(1024, [1, 2, 4], 512, "u16", 100, None)
+    assert nfs.workspace_size(1024, [1, 2, 4], 512, capacity=100) > limit
+    st = lib.nfs_structure_function_noalloc(ctypes.byref(d), ctypes.c_void_p(16), 100,
+                                            ctypes.c_void_p(16), None, None, None, None)
+    assert nfs.status_name(st) == "NFS_E_SCRATCH"
+    # capacity 0 takes what the array holds; at 1024^2 even the smallest ring
+    # (largest lag + 1 slots) does not fit beside the batch intermediate.
+    d, _keep = nfs.nfs._desc(1024, list(range(1, 200)), 512, "u16", 0, None)
+    st = lib.nfs_structure_function_noalloc(ctypes.byref(d), ctypes.c_void_p(16), 10,
+                                            ctypes.c_void_p(16), None, None, None, None)
+    assert nfs.status_name(st) == "NFS_E_SCRATCH"
+    ok, _keep = nfs.nfs._desc(128, [1, 2], 64, "f32", 64, None)
+    assert nfs.workspace_size(128, [1, 2], 64, in_dtype="f32", capacity=64) <= limit
+    assert lib.nfs_structure_function_noalloc(None, ctypes.c_void_p(16), 1, ctypes.c_void_p(16),
+                                              None, None, None, None) == 1
+    assert lib.nfs_structure_function_noalloc(ctypes.byref(ok), None, 1, ctypes.c_void_p(16),
+                                              None, None, None, None) == 1
+    assert lib.nfs_structure_function_noalloc(ctypes.byref(ok), ctypes.c_void_p(16), 1, None,
+                                              None, None, None, None) == 1
+    assert lib.nfs_structure_function_noalloc(ctypes.byref(ok), ctypes.c_void_p(16), -1,
+                                              ctypes.c_void_p(16), None, None, None, None) == 1
+    staged, _k2 = nfs.nfs._desc(128, [1, 2], 64, "f32", 64, None, host_staging=True)
+    assert lib.nfs_structure_function_noalloc(ctypes.byref(staged), ctypes.c_void_p(16), 1,
+                                              ctypes.c_void_p(16), None, None, None, None) == 1
+    bad, _k3 = nfs.nfs._desc(100, [1, 2], 50, "f32", 64, None)
+    assert nfs.status_name(lib.nfs_structure_function_noalloc(
+        ctypes.byref(bad), ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None, None, None,
+        None)) == "NFS_E_SIZE"
