@@ -371,7 +371,11 @@ def differentiation(args):
     frames = gen.make_stack(cfg, args.seed, device="cuda")
     w = torch.from_numpy(np.outer(np.hanning(n), np.hanning(n)).astype(np.float32)).cuda()
     G = torch.from_numpy(np.random.default_rng(args.seed).standard_normal((len(lags), nb))).cuda()
-    plan = nfs.Plan(n, lags, nb, in_dtype="f32", capacity=N, window=w, backward=True,
+    # --capacity below N: the ring holds fewer spectra than frames and the
+    # backward recomputes them from the frames (needs capacity > 2 x 64).
+    capacity = args.capacity or N
+    recompute = capacity < N
+    plan = nfs.Plan(n, lags, nb, in_dtype="f32", capacity=capacity, window=w, backward=True,
                     spec=args.spec, accum=args.accum)
     stream = plan.stream
     out = plan.empty_outputs()
@@ -402,27 +406,42 @@ def differentiation(args):
     for i in range(args.steps):
         step(evs[i])
     torch.cuda.synchronize()
-    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
-    ms_fwd = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps
-    ms_bwd = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    ms_wall = (time.perf_counter() - t0) * 1e3 / args.steps
+    import statistics
+    ms_step = statistics.median(e[0].elapsed_time(e[2]) for e in evs)
+    ms_fwd = statistics.median(e[0].elapsed_time(e[1]) for e in evs)
+    ms_bwd = statistics.median(e[1].elapsed_time(e[2]) for e in evs)
     assert bool(torch.isfinite(gf).all()) and bool(torch.isfinite(gw).all())
     pairs = frame_pairs(N, lags)
     M = plan.modes
-    # Backward algorithmic traffic: the resident spectra read once, the
-    # frames read once, the frame gradient written once.
-    bwd_bytes = N * M * (8 if args.spec == "f32" else 4) + 2 * N * n * n * 4
+    # Backward algorithmic traffic: the stored spectra read once, the frames
+    # read once, the frame gradient written once; recomputing adds one more
+    # read of the frames and one write of the spectra.
+    spec_bytes = N * M * (8 if args.spec == "f32" else 4)
+    bwd_bytes = spec_bytes + 2 * N * n * n * 4
+    if recompute:
+        bwd_bytes += spec_bytes + N * n * n * 4
     plan.close()
     print(json.dumps({
         "metric": METRIC_C5, "value": pairs / (ms_step * 1e-3), "unit": "frame-pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "ms_per_step_stat": "median of per-step HIP-event times", "ms_per_step_mean_wall": ms_wall,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS["c5"] + ", seed %d" % args.seed, "frames": N, "n": n,
                    "lags": len(lags), "n_bins": nb, "frame_pairs": pairs, "stored_modes": M,
-                   "spectra": args.spec, "accumulation": args.accum,
+                   "spectra": args.spec, "accumulation": args.accum, "capacity": capacity,
+                   "backward_spectra": "recomputed" if recompute else "resident",
                    "parallelism": "single GPU"},
         "stage_ms": {"forward": ms_fwd, "backward": ms_bwd},
         "backward_gbps_algorithmic": bwd_bytes / (ms_bwd * 1e-3) / 1e9,
+        "roofline": {"kernel": "nfs_backward (k-space gradient, inverse transforms, "
+                               "normalisation adjoint" + (", spectra recomputed" if recompute
+                                                          else "") + ")",
+                     "bound": "hbm", "achieved": bwd_bytes / (ms_bwd * 1e-3) / 1e9,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": bwd_bytes / (ms_bwd * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                     "algorithmic_bytes_per_step": bwd_bytes, "traffic": None},
     }))
 
 

@@ -216,11 +216,16 @@ nfs_status nfs_power_spectra_2d(nfs_handle h, float* S);
  * depend on the frames there). N is the number of frames pushed so far;
  * `frames` must be those frames, device [N][n][n] of the plan's pixel type
  * (the normalisation and window adjoints need the pixels). The k-space
- * gradient is formed from the resident spectra, so every pushed frame must
- * still be in the ring (capacity >= N), else NFS_E_STATE; the plan needs
- * desc.backward = 1, else NFS_E_STATE. FP32 transforms and differences,
- * FP64 sums of pixels and of the window gradient. Enqueued on the plan's
- * stream; the plan's sums are not changed. */
+ * gradient is formed from the stored spectra: from the resident ones when
+ * the ring still holds every pushed frame (capacity >= N); otherwise they
+ * are recomputed from `frames` by the forward transform (one more transform
+ * per frame, in windows of targets plus the largest lag either side), which
+ * needs capacity > 2 x the largest lag, else NFS_E_CAPACITY. Recomputing
+ * leaves the ring as the pushes left it (the last `capacity` frames), so
+ * frames can still be pushed afterwards. The plan needs desc.backward = 1,
+ * else NFS_E_STATE. FP32 transforms and differences, FP64 sums of pixels
+ * and of the window gradient. Enqueued on the plan's stream; the plan's
+ * sums are not changed. */
 nfs_status nfs_backward(nfs_handle h, const double* dL_dD, const void* frames,
                         float* dL_dframes, float* dL_dwindow);
 

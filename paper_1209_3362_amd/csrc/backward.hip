@@ -47,15 +47,22 @@ __global__ void grad_table_kernel(int n_lags, int n_bins, const double* __restri
   gtab[i] = (tau > 0 && np > 0 && C > 0) ? float(dL_dD[i] / (double(C) * double(np))) : 0.f;
 }
 
-// Stored value of frame t at mode m, as the pair kernel pairs it. Every
-// frame of the sequence is in the ring (t < capacity), so frame t is in
-// slot t.
+// Ring slot of frame t inside the window of frames [tw0, tw0 + capacity)
+// that the ring holds during one batch of the backward: slot0 is the slot of
+// frame tw0 (tw0 mod capacity), so no 64-bit modulo is taken per load.
+__device__ __forceinline__ int64_t window_slot(int64_t t, int64_t tw0, int64_t slot0,
+                                               int64_t capacity) {
+  const int64_t s = slot0 + (t - tw0);
+  return s >= capacity ? s - capacity : s;
+}
+
+// Stored value of the frame in `slot` at mode m, as the pair kernel pairs
+// it.
 template <int SPEC>
 __device__ __forceinline__ float2 stored_value(const char* __restrict__ ring,
                                                const float4* __restrict__ fscale,
                                                const float2* __restrict__ refspec,
-                                               int64_t mode_stride, int64_t t, int64_t m) {
-  const int64_t slot = t;
+                                               int64_t mode_stride, int64_t slot, int64_t m) {
   const float4 sc = fscale[slot];
   float2 a;
   if constexpr (SPEC == kSpecF32) {
@@ -79,7 +86,7 @@ __global__ __launch_bounds__(256) void grad_spectra_kernel(
     const float2* __restrict__ refspec, int64_t capacity, int64_t mode_stride, int64_t n_modes,
     const int32_t* __restrict__ mode_bin, const float* __restrict__ gtab,
     const int32_t* __restrict__ lags, int n_lags, int n_bins, int64_t n_frames, int64_t t0,
-    int nframes, float2* __restrict__ gk) {
+    int nframes, int64_t tw0, int64_t slot0, float2* __restrict__ gk) {
   const int xcd = blockIdx.x % 8, local = blockIdx.x / 8;
   const int tile = xcd + 8 * (local / nframes);
   const int f = local % nframes;
@@ -91,7 +98,8 @@ __global__ __launch_bounds__(256) void grad_spectra_kernel(
     gk[int64_t(f) * mode_stride + m] = make_float2(0.f, 0.f);
     return;
   }
-  const float2 at = stored_value<SPEC>(ring, fscale, refspec, mode_stride, t, m);
+  const float2 at = stored_value<SPEC>(ring, fscale, refspec, mode_stride,
+                                       window_slot(t, tw0, slot0, capacity), m);
   float gx = 0.f, gy = 0.f;
   for (int l = 0; l < n_lags; ++l) {
     const float c = gtab[l * n_bins + b];
@@ -99,14 +107,14 @@ __global__ __launch_bounds__(256) void grad_spectra_kernel(
     const int64_t tau = lags[l];
     float dx = 0.f, dy = 0.f;
     if (t + tau < n_frames) {
-      const float2 o =
-          stored_value<SPEC>(ring, fscale, refspec, mode_stride, t + tau, m);
+      const float2 o = stored_value<SPEC>(ring, fscale, refspec, mode_stride,
+                                          window_slot(t + tau, tw0, slot0, capacity), m);
       dx += at.x - o.x;
       dy += at.y - o.y;
     }
     if (t >= tau) {
-      const float2 o =
-          stored_value<SPEC>(ring, fscale, refspec, mode_stride, t - tau, m);
+      const float2 o = stored_value<SPEC>(ring, fscale, refspec, mode_stride,
+                                          window_slot(t - tau, tw0, slot0, capacity), m);
       dx += at.x - o.x;
       dy += at.y - o.y;
     }
@@ -126,10 +134,10 @@ constexpr int kFB = 64;
 template <int SPEC, int KM>
 __global__ __launch_bounds__(256) void grad_spectra_lds_kernel(
     const char* __restrict__ ring, const float4* __restrict__ fscale,
-    const float2* __restrict__ refspec, int64_t mode_stride, int64_t n_modes,
+    const float2* __restrict__ refspec, int64_t capacity, int64_t mode_stride, int64_t n_modes,
     const int32_t* __restrict__ mode_bin, const float* __restrict__ gtab,
     const int32_t* __restrict__ lags, int n_lags, int n_bins, int max_lag, int64_t n_frames,
-    int64_t t0, int nframes, float2* __restrict__ gk) {
+    int64_t t0, int nframes, int64_t tw0, int64_t slot0, float2* __restrict__ gk) {
   constexpr int G = 256 / KM, KP = KM + 1, NO = kFB / G;
   extern __shared__ float2 win[];
   const int fblocks = (nframes + kFB - 1) / kFB;
@@ -140,11 +148,13 @@ __global__ __launch_bounds__(256) void grad_spectra_lds_kernel(
   const int64_t tlo = max(int64_t(0), tfirst - max_lag);
   const int64_t thi = min(n_frames, tlast + max_lag);
   const int rows = int(thi - tlo);
+  const int64_t slot_lo = window_slot(tlo, tw0, slot0, capacity);
   for (int idx = threadIdx.x; idx < rows * KM; idx += 256) {
     const int r = idx / KM, j = idx % KM;
     const int64_t m = m0 + j;
+    const int64_t slot = slot_lo + r < capacity ? slot_lo + r : slot_lo + r - capacity;
     win[r * KP + j] = m < n_modes
-                          ? stored_value<SPEC>(ring, fscale, refspec, mode_stride, tlo + r, m)
+                          ? stored_value<SPEC>(ring, fscale, refspec, mode_stride, slot, m)
                           : make_float2(0.f, 0.f);
   }
   __syncthreads();
@@ -414,8 +424,8 @@ hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
                                const float2* refspec, int64_t capacity, int64_t mode_stride,
                                int64_t n_modes, const int32_t* mode_bin, const float* gtab,
                                const int32_t* lags, int n_lags, int n_bins, int max_lag,
-                               int64_t n_frames, int64_t t0, int nframes, float2* gk,
-                               hipStream_t s) {
+                               int64_t n_frames, int64_t t0, int nframes, int64_t tw0,
+                               int64_t slot0, float2* gk, hipStream_t s) {
   // The windowed kernel when a window of kFB targets plus the lags either
   // side fits 64 KB of LDS with 16 or 8 slots per workgroup (16 measured
   // faster than 32, which holds half as many workgroups per CU, and than 8).
@@ -425,9 +435,9 @@ hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
 #define NFS_GRADW_GO(SPECV, KMV)                                                              \
   hipLaunchKernelGGL((grad_spectra_lds_kernel<SPECV, KMV>),                                   \
                      dim3(unsigned(((n_modes + KMV - 1) / KMV) * fblocks)), dim3(256),         \
-                     size_t(rows) * (KMV + 1) * 8, s, rr, fscale, refspec, mode_stride,        \
-                     n_modes, mode_bin, gtab, lags, n_lags, n_bins, max_lag, n_frames, t0,     \
-                     nframes, gk)
+                     size_t(rows) * (KMV + 1) * 8, s, rr, fscale, refspec, capacity,          \
+                     mode_stride, n_modes, mode_bin, gtab, lags, n_lags, n_bins, max_lag,      \
+                     n_frames, t0, nframes, tw0, slot0, gk)
 #define NFS_GRADW_KM(KMV)                                                                     \
   if (rows * (KMV + 1) * 8 <= 64 * 1024) {                                                    \
     if (spec == kSpecF32) NFS_GRADW_GO(kSpecF32, KMV);                                        \
@@ -446,7 +456,7 @@ hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
 #define NFS_GRAD_GO(SPECV)                                                                    \
   hipLaunchKernelGGL(grad_spectra_kernel<SPECV>, grid, dim3(256), 0, s, r, fscale, refspec,  \
                      capacity, mode_stride, n_modes, mode_bin, gtab, lags, n_lags, n_bins,   \
-                     n_frames, t0, nframes, gk)
+                     n_frames, t0, nframes, tw0, slot0, gk)
   if (spec == kSpecF32)
     NFS_GRAD_GO(kSpecF32);
   else if (spec == kSpecBF16)

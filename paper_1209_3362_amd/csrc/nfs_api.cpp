@@ -162,6 +162,21 @@ nfs_status make_room(nfs_plan_s* h, int64_t b) {
 }
 
 // Normalise, transform and store `b` frames (device memory, b <= the batch
+// size, after the reference frame is set) as frames [t, t + b), each in
+// ring slot (its frame index) mod capacity.
+nfs_status transform_into_ring(nfs_plan_s* h, const char* src, int64_t b, int64_t t) {
+  const nfs::Layout& L = h->L;
+  hipError_t e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->ref, h->window, int(b),
+                                      h->inter, h->rowsum, h->rowabs, h->tw, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
+  e = nfs::launch_col_pass(L.n, false, L.spec_dtype, h->inter, h->rowsum, h->rowabs, int(b), t,
+                           L.capacity, L.mode_stride, L.slots, h->tiles, h->tw, h->ring,
+                           h->refspec, h->refscal, h->fscale, h->status, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
+  return NFS_OK;
+}
+
+// Normalise, transform and store `b` frames (device memory, b <= the batch
 // size) as frames [t_pushed, t_pushed + b); make_room must precede it.
 nfs_status transform_batch(nfs_plan_s* h, const char* src, int64_t b) {
   const nfs::Layout& L = h->L;
@@ -182,14 +197,8 @@ nfs_status transform_batch(nfs_plan_s* h, const char* src, int64_t b) {
                                h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "reference transform launch");
   }
-  e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->ref, h->window, int(b), h->inter,
-                           h->rowsum, h->rowabs, h->tw, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
-  e = nfs::launch_col_pass(L.n, false, L.spec_dtype, h->inter, h->rowsum, h->rowabs, int(b),
-                           h->t_pushed, L.capacity, L.mode_stride, L.slots, h->tiles,
-                           h->tw, h->ring, h->refspec, h->refscal, h->fscale,
-                           h->status, h->stream);
-  if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
+  nfs_status st = transform_into_ring(h, src, b, h->t_pushed);
+  if (st != NFS_OK) return st;
   h->t_pushed += b;
   return NFS_OK;
 }
@@ -492,18 +501,44 @@ nfs_status nfs_backward(nfs_handle h, const double* dL_dD, const void* frames,
   if (!frames) return fail(h, NFS_E_ARG, "frames is NULL");
   const int64_t N = h->t_pushed;
   if (N < 1) return fail(h, NFS_E_STATE, "no frame pushed");
-  if (N > L.capacity)
-    return fail(h, NFS_E_STATE, "the gradient needs every pushed frame in the ring (capacity >= frames)");
+  // When the ring no longer holds every frame, the spectra are recomputed
+  // from `frames` by the forward passes, window by window: targets
+  // [t0, t0 + b) need frames [t0 - max_lag, t0 + b + max_lag), so b is at
+  // most capacity - 2 max_lag, and each frame is transformed once more.
+  // The last window leaves frames [N - capacity, N) in their slots, as the
+  // pushes did, so later pushes and pair sums see the same ring.
+  const bool recompute = N > L.capacity;
+  int64_t bb = L.batch;
+  if (recompute) {
+    const int64_t room = L.capacity - 2 * int64_t(L.max_lag);
+    if (room < 1)
+      return fail(h, NFS_E_CAPACITY,
+                  "recomputing spectra for the gradient needs capacity > 2 x the largest lag");
+    if (room < bb) bb = room;
+  }
   const int64_t px = int64_t(L.n) * L.n;
   hipError_t e = nfs::launch_grad_table(L.n_lags, L.n_bins, dL_dD, h->bin_count, h->lags, N,
                                         h->gtab, h->stream);
   if (e == hipSuccess && dL_dwindow) e = nfs::launch_fill_u32(h->gw, size_t(px) * 2, 0u, h->stream);
-  for (int64_t t0 = 0; e == hipSuccess && t0 < N; t0 += L.batch) {
-    const int b = int(N - t0 < L.batch ? N - t0 : L.batch);
+  int64_t have = 0;  // frames [0, have) recomputed by this call
+  for (int64_t t0 = 0; e == hipSuccess && t0 < N; t0 += bb) {
+    const int b = int(N - t0 < bb ? N - t0 : bb);
     const char* fr = static_cast<const char*>(frames) + size_t(t0) * L.frame_bytes;
+    if (recompute) {
+      const int64_t need = t0 + b + L.max_lag < N ? t0 + b + L.max_lag : N;
+      while (have < need) {
+        const int64_t c = need - have < L.batch ? need - have : L.batch;
+        nfs_status st = transform_into_ring(
+            h, static_cast<const char*>(frames) + size_t(have) * L.frame_bytes, c, have);
+        if (st != NFS_OK) return st;
+        have += c;
+      }
+    }
+    const int64_t tw0 = t0 - L.max_lag > 0 ? t0 - L.max_lag : 0;
     e = nfs::launch_grad_spectra(h->ring, L.spec_dtype, h->fscale, h->refspec, L.capacity,
                                  L.mode_stride, L.slots, h->mode_bin, h->gtab, h->lags,
-                                 L.n_lags, L.n_bins, L.max_lag, N, t0, b, h->gk, h->stream);
+                                 L.n_lags, L.n_bins, L.max_lag, N, t0, b, tw0,
+                                 tw0 % L.capacity, h->gk, h->stream);
     if (e == hipSuccess)
       e = nfs::launch_inverse_2d(L.n, L.in_dtype, h->gk, L.mode_stride, h->width, h->tiles,
                                  h->tw, b, h->inter, reinterpret_cast<float*>(h->gk), fr,

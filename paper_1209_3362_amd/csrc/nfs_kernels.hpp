@@ -106,14 +106,16 @@ hipError_t launch_grad_table(int n_lags, int n_bins, const double* dL_dD,
 
 // k-space gradient of frames [t0, t0 + nframes) on the stored modes:
 // gk[f][m] = 2 sum_l gtab[l][mode_bin[m]] * ([t + lag < N] (a_t - a_{t+lag})
-// + [t >= lag] (a_t - a_{t-lag})), a_t decoded as by the pair kernel. Every
-// frame of [0, N) must be in the ring.
+// + [t >= lag] (a_t - a_{t-lag})), a_t decoded as by the pair kernel. The
+// frames [max(0, t0 - max_lag), min(N, t0 + nframes + max_lag)) must be in
+// the ring, frame tw0 in slot slot0 and frame tw0 + i in slot
+// (slot0 + i) mod capacity (a window of at most capacity frames).
 hipError_t launch_grad_spectra(const void* ring, int spec, const float4* fscale,
                                const float2* refspec, int64_t capacity, int64_t mode_stride,
                                int64_t n_modes, const int32_t* mode_bin, const float* gtab,
                                const int32_t* lags, int n_lags, int n_bins, int max_lag,
-                               int64_t n_frames, int64_t t0, int nframes, float2* gk,
-                               hipStream_t s);
+                               int64_t n_frames, int64_t t0, int nframes, int64_t tw0,
+                               int64_t slot0, float2* gk, hipStream_t s);
 
 // Adjoint of the 2D transform for nframes frames: inverse column transforms
 // of gk (stored modes, [nframes][mode_stride]) into z (n x n/2 complex per

@@ -372,10 +372,12 @@ class _StructureFunction(torch.autograd.Function):
     backward calls nfs_backward on the same plan."""
 
     @staticmethod
-    def forward(ctx, frames, window, lags, n_bins, spec, accum):
+    def forward(ctx, frames, window, lags, n_bins, spec, accum, capacity):
         in_dtype = "u16" if frames.dtype == torch.uint16 else "f32"
         N, n = frames.shape[0], frames.shape[-1]
-        plan = Plan(n, lags, n_bins, in_dtype=in_dtype, capacity=max(N, max(lags) + 1),
+        if not capacity:
+            capacity = max(N, max(lags) + 1)
+        plan = Plan(n, lags, n_bins, in_dtype=in_dtype, capacity=capacity,
                     window=None if window is None else window.detach(), spec=spec,
                     accum=accum, backward=True, device=frames.device)
         frames = frames.detach().contiguous()
@@ -396,14 +398,18 @@ class _StructureFunction(torch.autograd.Function):
         gf, gw = plan.backward(dD, frames, frames_grad=want_f, window_grad=want_w)
         plan.close()
         ctx.plan = None
-        return gf, gw, None, None, None, None
+        return gf, gw, None, None, None, None, None
 
 
-def structure_function(frames, lags, n_bins, window=None, spec="f32", accum="plain"):
+def structure_function(frames, lags, n_bins, window=None, spec="f32", accum="plain",
+                       capacity=None):
     """D [L][n_bins] (float64) of a device frame stack [N][n][n], differentiable
-    with respect to float32 frames and the window (torch autograd)."""
+    with respect to float32 frames and the window (torch autograd).
+    `capacity` is the plan's ring size in frames (default: the whole stack);
+    with fewer slots than frames the spectra are not kept for the backward
+    but recomputed there (needs capacity > 2 x the largest lag)."""
     return _StructureFunction.apply(frames, window, [int(t) for t in lags], int(n_bins), spec,
-                                    accum)
+                                    accum, int(capacity or 0))
 
 
 def probe_bandwidth(mode, src, dst, nbytes, stream=None):

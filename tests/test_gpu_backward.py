@@ -30,13 +30,15 @@ def _check(name, got, want, tol=1e-4):
     assert err <= tol * scale, (name, err / scale)
 
 
-def _run(frames, lags, n_bins, G, window, in_dtype="f32", spec="f32", chunk=None):
+def _run(frames, lags, n_bins, G, window, in_dtype="f32", spec="f32", chunk=None,
+         capacity=None):
     import paper_1209_3362_amd as nfs
     N, n = frames.shape[0], frames.shape[-1]
     t = frames.to("cuda")
     w = None if window is None else torch.from_numpy(window.astype(np.float32)).cuda()
-    plan = nfs.Plan(n, lags, n_bins, in_dtype=in_dtype, capacity=max(N, max(lags) + 1),
-                    window=w, spec=spec, backward=True)
+    cap = capacity or max(N, max(lags) + 1)
+    plan = nfs.Plan(n, lags, n_bins, in_dtype=in_dtype, capacity=cap, window=w, spec=spec,
+                    backward=True)
     if chunk:
         for i in range(0, N, chunk):
             plan.push(t[i:i + chunk])
@@ -129,8 +131,10 @@ def test_backward_from_16bit_spectra(spec, tol):
 
 def test_backward_differentiation_workload():
     """256 float32 frames of 512x512, Hann window, lags 1, 2, 4, ..., 64,
-    256 bins: against the oracle on every pixel, and the scale invariance of
-    D (sum_x i_t dL/di_t = 0 for every frame, sum_x w dL/dw = 0)."""
+    256 bins: with every spectrum resident and with a 160-slot ring (spectra
+    recomputed in the backward, 32 targets per window), against the oracle
+    on every pixel, and the scale invariance of D (sum_x i_t dL/di_t = 0 for
+    every frame, sum_x w dL/dw = 0)."""
     require_gpu()
     cfg = gen.config("c5")
     lags = cfg["lags"]
@@ -140,6 +144,8 @@ def test_backward_differentiation_workload():
     w = _hann(512)
     G = np.random.default_rng(5).standard_normal((len(lags), 256))
     gf, gw = _run(f, lags, 256, G, w)
+    say("backward: same stack, 160-slot ring, spectra recomputed")
+    rf, rw = _run(f, lags, 256, G, w, capacity=160)
     host = f.cpu().numpy()
     for t in (0, 100, 255):
         dot = float((host[t].astype(np.float64) * gf[t]).sum())
@@ -150,6 +156,99 @@ def test_backward_differentiation_workload():
     want = oracle.structure_function_grad(host, lags, 256, G, window=w)
     _check("frames", gf, want["frames"])
     _check("window", gw, want["window"])
+    _check("frames, recomputed", rf, want["frames"])
+    _check("window, recomputed", rw, want["window"])
+    # Recomputed spectra are the pushed ones bit for bit (same kernels on the
+    # same pixels), and each target's k-space gradient sums the same terms in
+    # the same order: the frame gradients agree exactly.
+    assert np.array_equal(rf, gf)
+
+
+@pytest.mark.parametrize("spec,tol", [("f32", 1e-4), ("f16", 3e-3)])
+def test_backward_recompute_matches_oracle(spec, tol):
+    """A ring of 20 slots under 40 frames (lags 0..8: windows of 4 targets,
+    spectra recomputed from the frames), chunked pushes, Hann window."""
+    require_gpu()
+    cfg = gen.config("c1", N=40)
+    lags = [0, 1, 2, 4, 8]
+    say(f"backward recompute ({spec}): 40 frames 128x128 f32, ring 20, lags 0..8, seed 48")
+    f = gen.make_stack(cfg, 48)
+    w = _hann(128) + 0.1
+    G = np.random.default_rng(48).standard_normal((len(lags), 64))
+    want = oracle.structure_function_grad(f.numpy(), lags, 64, G, window=w)
+    gf, gw = _run(f, lags, 64, G, w, spec=spec, chunk=7, capacity=20)
+    _check("frames", gf, want["frames"], tol=tol)
+    _check("window", gw, want["window"], tol=tol)
+
+
+def test_backward_recompute_long_lags_u16():
+    """Recompute with a largest lag of 450 (the global-memory gradient
+    kernel) over 1000 u16 frames in a 905-slot ring: windows of 5 targets."""
+    require_gpu()
+    lags = [1, 7, 450]
+    cfg = gen.config("c2", n=32, N=1000, n_bins=16)
+    say("backward recompute: 1000 frames 32x32 u16, ring 905, lags 1,7,450, seed 49")
+    f = gen.make_stack(cfg, 49)
+    G = np.random.default_rng(49).standard_normal((len(lags), 16))
+    want = oracle.structure_function_grad(f.numpy().astype(np.float64), lags, 16, G)
+    gf, gw = _run(f, lags, 16, G, None, in_dtype="u16", capacity=905)
+    _check("frames", gf, want["frames"])
+    _check("window", gw, want["window"])
+
+
+def test_backward_recompute_leaves_the_ring_as_pushed():
+    """After a recomputing backward the ring holds the last `capacity` frames
+    exactly as the pushes stored them: more pushes give the same D, bit for
+    bit, as a plan that never ran the backward."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfg = gen.config("c1", n=64, N=70, n_bins=32)
+    lags = [1, 2, 5, 9]
+    say("backward recompute: 50 + 20 frames 64x64 f32, ring 30, lags 1..9, seed 50")
+    f = gen.make_stack(cfg, 50).cuda()
+    G = torch.from_numpy(np.random.default_rng(50).standard_normal((len(lags), 32)))
+    out = []
+    for run_backward in (False, True):
+        plan = nfs.Plan(64, lags, 32, in_dtype="f32", capacity=30, backward=True)
+        plan.push(f[:50])
+        plan.structure_function()
+        before = [torch.empty(64, 32, 2, device="cuda") for _ in range(30)]
+        for i, t in enumerate(range(20, 50)):
+            plan._check(plan.lib.nfs_copy_spectrum(plan.handle, t,
+                                                   nfs.nfs._ptr(before[i])))
+        if run_backward:
+            plan.backward(G, f[:50])
+            for i, t in enumerate(range(20, 50)):
+                after = torch.empty(64, 32, 2, device="cuda")
+                plan._check(plan.lib.nfs_copy_spectrum(plan.handle, t, nfs.nfs._ptr(after)))
+                torch.cuda.synchronize()
+                assert torch.equal(after, before[i]), t
+        plan.push(f[50:])
+        D, C, P, st = plan.structure_function()
+        out.append(D.cpu().numpy())
+        plan.close()
+    assert np.array_equal(out[0], out[1])
+    ref = oracle.structure_function(f.cpu().numpy(), lags, 32)
+    assert np.allclose(out[1], ref["D"], rtol=1e-4, atol=0)
+
+
+def test_autograd_recompute():
+    """The autograd wrapper with a ring smaller than the stack."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfg = gen.config("c1", N=30)
+    lags = [1, 3, 6]
+    say("autograd recompute: 30 frames 128x128 f32, ring 16, learnable window, seed 51")
+    f = gen.make_stack(cfg, 51).cuda().requires_grad_(True)
+    w = torch.from_numpy(_hann(128).astype(np.float32) + 0.05).cuda().requires_grad_(True)
+    D = nfs.structure_function(f, lags, 64, window=w, capacity=16)
+    G = torch.randn(D.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(51))
+    (D * G.cuda()).sum().backward()
+    wn = w.detach().cpu().numpy().astype(np.float64)
+    want = oracle.structure_function_grad(f.detach().cpu().numpy(), lags, 64, G.numpy(),
+                                          window=wn)
+    _check("frames", f.grad.cpu().numpy(), want["frames"])
+    _check("window", w.grad.cpu().numpy(), want["window"])
 
 
 def test_autograd_function():
@@ -184,9 +283,11 @@ def test_backward_state_errors():
         plan.backward(G, f)
     assert e.value.status == 7
     plan.close()
-    plan = nfs.Plan(64, [1], 8, in_dtype="f32", capacity=4, backward=True)
+    # A ring of 2 slots under 6 frames cannot hold a target and its partners
+    # either side (capacity must exceed 2 x the largest lag to recompute).
+    plan = nfs.Plan(64, [1], 8, in_dtype="f32", capacity=2, backward=True)
     plan.push(f)
     with pytest.raises(nfs.NfsError) as e:
         plan.backward(G, f)
-    assert e.value.status == 7 and "capacity" in str(e.value)
+    assert e.value.status == 6 and "capacity" in str(e.value)
     plan.close()
