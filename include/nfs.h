@@ -52,9 +52,8 @@ typedef enum {
   NFS_OK = 0,
   NFS_E_ARG = 1,              /* null pointer or invalid enum value          */
   NFS_E_SIZE = 2,             /* n not a power of two in [16, 4096]          */
-  NFS_E_LAGS = 3,             /* lags empty, negative, unsorted, duplicated,
-                                 or the largest lag beyond what the pair
-                                 kernel's on-chip history can hold (2400)    */
+  NFS_E_LAGS = 3,             /* lags empty, negative, unsorted or
+                                 duplicated                                  */
   NFS_E_BINS = 4,             /* n_bins outside [1, n/2]                     */
   NFS_E_WORKSPACE = 5,        /* workspace null, misaligned or too small     */
   NFS_E_CAPACITY = 6,         /* ring capacity negative, not larger than the
@@ -116,6 +115,13 @@ typedef struct {
                            batch of k-space gradients, per-row sums, an FP64
                            window-gradient accumulator and per-mode bin
                            tables                                            */
+  int32_t full_spectra; /* 0: store and pair only the modes that land in a
+                           ring (k_x < n/2, |k| < n/2), enough for D; 1: also
+                           the rest of the half plane (the corners |k| >= n/2
+                           and the k_x = n/2 column), so nfs_power_spectra_2d
+                           returns the entire 2D spectra (discussion section).
+                           D is the same either way; 1 costs about 27 % more
+                           ring memory, transform stores and pair work        */
 } nfs_desc;
 
 /* Bytes of device workspace nfs_plan needs for `desc`. Host only; enqueues
@@ -196,11 +202,13 @@ nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
  * write, on the device, S float [n_lags][n][n/2 + 1]: entry [l][r][k_x] is
  *   P_tau(k) = (1 / (N - tau)) * sum_t |I_t(k) - I_{t+tau}(k)|^2
  * for tau = lags[l] and the mode (k_y, k_x), r the transform-order row of
- * k_y, at the stored modes (k_x < n/2, |k| < n/2); 0 at the other modes
- * (the k_x = n/2 column and the corners, which belong to no bin); NaN for
- * every mode of a delay with no pair (N - tau <= 0). The sums are FP32 per
- * mode, the division is done in double and rounded once. S is owned by the
- * caller. Enqueued on the plan's stream. */
+ * k_y, at every mode of the half plane for a plan made with
+ * desc.full_spectra = 1; otherwise at the stored modes (k_x < n/2,
+ * |k| < n/2) and 0 at the others (the k_x = n/2 column and the corners,
+ * which belong to no bin); NaN for every mode of a delay with no pair
+ * (N - tau <= 0). The sums are FP32 per mode, the division is done in
+ * double and rounded once. S is owned by the caller. Enqueued on the
+ * plan's stream. */
 nfs_status nfs_power_spectra_2d(nfs_handle h, float* S);
 
 /* Differentiation form: gradients of a scalar loss L of D with respect to

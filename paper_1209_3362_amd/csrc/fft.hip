@@ -81,7 +81,8 @@ __device__ __forceinline__ typename RawPair<T>::type load_pair(const T* p) {
 // Row pass. Real row u of N pixels (minus the reference row, times the
 // window) -> z[j] = u[2j] + i u[2j+1] (H points), Z = DFT_H(z), then
 // X[k] = (Z[k] + conj Z[H-k])/2 - i W_N^k (Z[k] - conj Z[H-k])/2 for
-// k = 0..H-1 (the real-input split; X[H] is never binned). A row's P1
+// k = 0..H-1 (the real-input split; X[H], never binned, is written to
+// nyq[f][y] only for full half-plane plans, nyq not null). A row's P1
 // threads sit in one wave and only they touch the row's LDS, so the frame
 // loop has no workgroup barrier. A workgroup owns R rows and loops over up
 // to `per_group` frames of the batch, loading the next frame's pixels while
@@ -91,7 +92,7 @@ template <int N, typename T, bool WIN, bool ABS>
 __global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN, ABS>())) void row_pass_kernel(
     const T* __restrict__ frames, const T* __restrict__ ref, const float* __restrict__ window,
     int nframes, int per_group, float2* __restrict__ inter, double* __restrict__ rowsum,
-    double* __restrict__ rowabs, const float2* __restrict__ tw) {
+    double* __restrict__ rowabs, float* __restrict__ nyq, const float2* __restrict__ tw) {
   using C = RowCfg<N>;
   using Raw = typename RawPair<T>::type;
   constexpr bool U16 = std::is_same<T, uint16_t>::value;
@@ -233,6 +234,11 @@ __global__ __launch_bounds__(RowCfg<N>::THREADS, (row_min_waves<N, T, WIN, ABS>(
       for (int k1 = 0; k1 < P1; ++k1) row_lds[(j1 + q * P1) + P2 * k1] = z[q][k1];
     wave_lds_sync();
 
+    // k_x = n/2 (full half-plane plans): X[H] = Re Z[0] - Im Z[0], real.
+    if (nyq && j1 == 0) {
+      const float2 z0 = row_lds[0];
+      nyq[int64_t(f) * N + y] = z0.x - z0.y;
+    }
     // Real-input split of this thread's outputs k = j1 + P1 i, stored into
     // the intermediate: column k % TWD of row y of tile k / TWD.
     float2* frame_out = inter + int64_t(f) * TILES * N * TWD;
@@ -466,10 +472,63 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
   }
 }
 
+// ---------------------------------------------------------------------------
+// The k_x = n/2 column of full half-plane plans, one workgroup per frame:
+// Y(k_y) = sum_y x[y] W_n^{k_y y} of the row pass's real values x[y] =
+// X_y(n/2), by an iterative radix-2 transform in LDS (bit-reversed load,
+// log2 n butterfly stages, twiddles from the plan's table), stored at slot
+// nyq_slot + r of the frame's spectrum, r = k_y mod n. REF: the reference
+// frame's values, unscaled FP32 into refspec. Otherwise frame t0 + f,
+// scaled and encoded exactly as the column pass did its other modes, with
+// sigma and the FP16 scale that pass wrote to fscale[slot] (it runs first
+// on the stream): sigma 2^e = fscale.x / fscale.z.
+template <bool REF, int SPEC>
+__global__ __launch_bounds__(256) void nyquist_col_kernel(
+    int n, const float* __restrict__ nyq, const float2* __restrict__ tw,
+    const float4* __restrict__ fscale, int64_t t0, int64_t capacity, int64_t mode_stride,
+    int64_t nyq_slot, char* __restrict__ ring, float2* __restrict__ refspec) {
+  extern __shared__ float2 buf[];
+  const int f = blockIdx.x;
+  const int lg = __builtin_ctz(uint32_t(n));
+  for (int y = threadIdx.x; y < n; y += blockDim.x) {
+    const int rv = int(__brev(uint32_t(y)) >> (32 - lg));
+    buf[rv] = make_float2(nyq[int64_t(f) * n + y], 0.f);
+  }
+  __syncthreads();
+  for (int half = 1; half < n; half <<= 1) {
+    const int step = n / (2 * half);  // twiddle W_n^{j step} = W_{2 half}^j
+    for (int b = threadIdx.x; b < n / 2; b += blockDim.x) {
+      const int j = b % half;
+      const int i0 = (b / half) * 2 * half + j;
+      const float2 a = buf[i0];
+      const float2 c = cmul(buf[i0 + half], tw[j * step]);
+      buf[i0] = make_float2(a.x + c.x, a.y + c.y);
+      buf[i0 + half] = make_float2(a.x - c.x, a.y - c.y);
+    }
+    __syncthreads();
+  }
+  if constexpr (REF) {
+    for (int r = threadIdx.x; r < n; r += blockDim.x) refspec[nyq_slot + r] = buf[r];
+  } else {
+    const int64_t slot = (t0 + f) % capacity;
+    const float4 sc = fscale[slot];
+    const float scale = sc.x == 0.f ? 0.f : sc.x / sc.z;  // sigma 0: degenerate frame
+    char* base = ring + slot * mode_stride * int64_t(SPEC == kSpecF32 ? 8 : 4);
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      const float2 X = make_float2(buf[r].x * scale, buf[r].y * scale);
+      if constexpr (SPEC == kSpecF32)
+        reinterpret_cast<float2*>(base)[nyq_slot + r] = X;
+      else
+        reinterpret_cast<uint32_t*>(base)[nyq_slot + r] =
+            SPEC == kSpecBF16 ? pack_bf16(X) : pack_f16(X);
+    }
+  }
+}
+
 template <int N, typename T, bool WIN>
 hipError_t row_launch(const void* frames, const void* ref, const float* window, int nframes,
-                      float2* inter, double* rowsum, double* rowabs, const float2* tw,
-                      hipStream_t s) {
+                      float2* inter, double* rowsum, double* rowabs, float* nyq,
+                      const float2* tw, hipStream_t s) {
   using C = RowCfg<N>;
   const int per = frames_per_group(nframes, C::RB);
   const int64_t blocks = int64_t(C::RB) * ((nframes + per - 1) / per);
@@ -477,30 +536,30 @@ hipError_t row_launch(const void* frames, const void* ref, const float* window, 
     hipLaunchKernelGGL((row_pass_kernel<N, T, WIN, true>), dim3(unsigned(blocks)),
                        dim3(C::THREADS), 0, s, static_cast<const T*>(frames),
                        static_cast<const T*>(ref), window, nframes, per, inter, rowsum, rowabs,
-                       tw);
+                       nyq, tw);
   } else {
     hipLaunchKernelGGL((row_pass_kernel<N, T, WIN, false>), dim3(unsigned(blocks)),
                        dim3(C::THREADS), 0, s, static_cast<const T*>(frames),
                        static_cast<const T*>(ref), window, nframes, per, inter, rowsum, rowabs,
-                       tw);
+                       nyq, tw);
   }
   return hipGetLastError();
 }
 
 template <int N>
 hipError_t row_dispatch(int in_dtype, const void* frames, const void* ref, const float* window,
-                        int nframes, float2* inter, double* rowsum, double* rowabs,
+                        int nframes, float2* inter, double* rowsum, double* rowabs, float* nyq,
                         const float2* tw, hipStream_t s) {
   if (in_dtype == 0) {
     return window ? row_launch<N, uint16_t, true>(frames, ref, window, nframes, inter, rowsum,
-                                                  rowabs, tw, s)
+                                                  rowabs, nyq, tw, s)
                   : row_launch<N, uint16_t, false>(frames, ref, window, nframes, inter, rowsum,
-                                                   rowabs, tw, s);
+                                                   rowabs, nyq, tw, s);
   }
   return window ? row_launch<N, float, true>(frames, ref, window, nframes, inter, rowsum,
-                                             rowabs, tw, s)
+                                             rowabs, nyq, tw, s)
                 : row_launch<N, float, false>(frames, ref, window, nframes, inter, rowsum,
-                                              rowabs, tw, s);
+                                              rowabs, nyq, tw, s);
 }
 
 template <int N>
@@ -536,11 +595,11 @@ hipError_t col_launch(bool reference, int spec, const float2* inter, const doubl
 
 hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* ref,
                            const float* window, int nframes, float2* inter, double* rowsum,
-                           double* rowabs, const float2* tw, hipStream_t s) {
+                           double* rowabs, float* nyq, const float2* tw, hipStream_t s) {
 #define NFS_ROW_CASE(NN)                                                                    \
   case NN:                                                                                  \
     return row_dispatch<NN>(in_dtype, frames, ref, window, nframes, inter, rowsum, rowabs, \
-                            tw, s);
+                            nyq, tw, s);
   switch (n) {
     NFS_ROW_CASE(16)
     NFS_ROW_CASE(32)
@@ -554,6 +613,29 @@ hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* 
     default: return hipErrorInvalidValue;
   }
 #undef NFS_ROW_CASE
+}
+
+hipError_t launch_nyquist_col(int n, bool reference, int spec, const float* nyq, int nframes,
+                              int64_t t0, int64_t capacity, int64_t mode_stride,
+                              int64_t nyq_slot, const float2* tw, const float4* fscale,
+                              void* ring, float2* refspec, hipStream_t s) {
+  if (nframes < 1) return hipSuccess;
+  const size_t lds = size_t(n) * sizeof(float2);
+  char* ringb = static_cast<char*>(ring);
+#define NFS_NYQ_GO(REFV, SPECV)                                                                \
+  hipLaunchKernelGGL((nyquist_col_kernel<REFV, SPECV>), dim3(unsigned(nframes)), dim3(256),  \
+                     lds, s, n, nyq, tw, fscale, t0, capacity, mode_stride, nyq_slot, ringb, \
+                     refspec)
+  if (reference)
+    NFS_NYQ_GO(true, kSpecF32);
+  else if (spec == kSpecBF16)
+    NFS_NYQ_GO(false, kSpecBF16);
+  else if (spec == kSpecF16)
+    NFS_NYQ_GO(false, kSpecF16);
+  else
+    NFS_NYQ_GO(false, kSpecF32);
+#undef NFS_NYQ_GO
+  return hipGetLastError();
 }
 
 hipError_t launch_col_pass(int n, bool reference, int spec, const float2* inter,

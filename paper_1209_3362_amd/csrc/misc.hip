@@ -60,10 +60,11 @@ __global__ void expand_kernel(int n, const char* __restrict__ spec_base, int spe
 
 // P_tau(k) = S_tau(k) / (N - tau) from the mode-major sums acc[mode][lag]
 // onto [n_lags][n][n/2 + 1]; 0 where no mode is stored, NaN for a delay
-// without pairs.
+// without pairs. nyq_slot >= 0: the k_x = n/2 column is stored, row r in
+// slot nyq_slot + r.
 __global__ void power_kernel(int n, int n_lags, const float* __restrict__ acc,
                              const int32_t* __restrict__ row_width,
-                             const int32_t* __restrict__ tiles,
+                             const int32_t* __restrict__ tiles, int64_t nyq_slot,
                              const int32_t* __restrict__ lags, int64_t n_frames,
                              float* __restrict__ out) {
   const int h = n / 2, w = h + 1;
@@ -81,6 +82,8 @@ __global__ void power_kernel(int n, int n_lags, const float* __restrict__ acc,
     } else if (kx < h && kx < row_width[r]) {
       const int64_t m = dev::ring_slot(n, tiles, r, kx);
       v = float(double(acc[m * n_lags + l]) / double(pairs));
+    } else if (kx == h && nyq_slot >= 0) {
+      v = float(double(acc[(nyq_slot + r) * n_lags + l]) / double(pairs));
     }
     out[i] = v;
   }
@@ -180,11 +183,11 @@ hipError_t launch_expand_spectrum(int n, const void* ring, int spec, int64_t slo
 }
 
 hipError_t launch_power_spectra(int n, int n_lags, const float* acc, const int32_t* row_width,
-                                const int32_t* tiles, const int32_t* lags,
+                                const int32_t* tiles, int64_t nyq_slot, const int32_t* lags,
                                 int64_t n_frames, float* out, hipStream_t s) {
   hipLaunchKernelGGL(power_kernel,
                      dim3(grid_for(int64_t(n_lags) * n * (n / 2 + 1), 256)), dim3(256), 0, s, n,
-                     n_lags, acc, row_width, tiles, lags, n_frames, out);
+                     n_lags, acc, row_width, tiles, nyq_slot, lags, n_frames, out);
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ struct nfs_plan_s {
   float2* inter = nullptr;
   double* rowsum = nullptr;
   double* rowabs = nullptr;     // row sums of |frame - reference| (FP16 storage)
+  float* nyq = nullptr;         // full plans: the row pass's k_x = n/2 values
   float* acc = nullptr;
   int32_t* status = nullptr;    // bit 0: a degenerate frame was pushed
   double* refscal = nullptr;    // {S_ref, sigma_ref} of the reference frame
@@ -167,12 +168,18 @@ nfs_status make_room(nfs_plan_s* h, int64_t b) {
 nfs_status transform_into_ring(nfs_plan_s* h, const char* src, int64_t b, int64_t t) {
   const nfs::Layout& L = h->L;
   hipError_t e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->ref, h->window, int(b),
-                                      h->inter, h->rowsum, h->rowabs, h->tw, h->stream);
+                                      h->inter, h->rowsum, h->rowabs, h->nyq, h->tw, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
   e = nfs::launch_col_pass(L.n, false, L.spec_dtype, h->inter, h->rowsum, h->rowabs, int(b), t,
                            L.capacity, L.mode_stride, L.slots, h->tiles, h->tw, h->ring,
                            h->refspec, h->refscal, h->fscale, h->status, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
+  if (L.full) {
+    e = nfs::launch_nyquist_col(L.n, false, L.spec_dtype, h->nyq, int(b), t, L.capacity,
+                                L.mode_stride, L.nyq_slot, h->tw, h->fscale, h->ring,
+                                h->refspec, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "Nyquist column launch");
+  }
   return NFS_OK;
 }
 
@@ -189,12 +196,16 @@ nfs_status transform_batch(nfs_plan_s* h, const char* src, int64_t b) {
     e = hipMemcpyAsync(h->ref, src, L.frame_bytes, hipMemcpyDeviceToDevice, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "reference copy");
     e = nfs::launch_row_pass(L.n, L.in_dtype, h->ref, nullptr, h->window, 1, h->inter,
-                             h->rowsum, nullptr, h->tw, h->stream);
+                             h->rowsum, nullptr, h->nyq, h->tw, h->stream);
     if (e == hipSuccess)
       e = nfs::launch_col_pass(L.n, true, NFS_SPEC_F32, h->inter, h->rowsum, nullptr, 1, 0,
                                L.capacity, L.mode_stride, L.slots, h->tiles, h->tw,
                                h->ring, h->refspec, h->refscal, h->fscale, h->status,
                                h->stream);
+    if (e == hipSuccess && L.full)
+      e = nfs::launch_nyquist_col(L.n, true, NFS_SPEC_F32, h->nyq, 1, 0, L.capacity,
+                                  L.mode_stride, L.nyq_slot, h->tw, h->fscale, h->ring,
+                                  h->refspec, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "reference transform launch");
   }
   nfs_status st = transform_into_ring(h, src, b, h->t_pushed);
@@ -261,6 +272,7 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->rowsum = reinterpret_cast<double*>(h->ws + L.off_rowsum);
   h->rowabs = L.spec_dtype == NFS_SPEC_F16 ? reinterpret_cast<double*>(h->ws + L.off_rowabs)
                                             : nullptr;
+  h->nyq = L.full ? reinterpret_cast<float*>(h->ws + L.off_nyq) : nullptr;
   h->acc = reinterpret_cast<float*>(h->ws + L.off_acc);
   h->status = reinterpret_cast<int32_t*>(h->ws + L.off_status);
   h->tw = reinterpret_cast<float2*>(h->ws + L.off_tw);
@@ -423,6 +435,7 @@ nfs_status nfs_tune_pairs(nfs_handle h, int32_t* choices, int32_t* groups) {
   if (e == hipSuccess) e = hipEventCreate(&e1);
   for (size_t gi = 0; e == hipSuccess && gi < h->groups.size(); ++gi) {
     const nfs::LagGroup cur = h->groups[gi];
+    if (cur.modes == 0) continue;  // long delays: one kernel shape only
     float best_ms = 0.f;
     nfs::LagGroup best = cur;
     for (const nfs::LagGroup& c : nfs::group_candidates(L.lags, cur.first, cur.count)) {
@@ -486,7 +499,8 @@ nfs_status nfs_power_spectra_2d(nfs_handle h, float* S) {
   nfs_status st = finish_sums(h);
   if (st != NFS_OK) return st;
   const nfs::Layout& L = h->L;
-  hipError_t e = nfs::launch_power_spectra(L.n, L.n_lags, h->acc, h->width, h->tiles, h->lags,
+  hipError_t e = nfs::launch_power_spectra(L.n, L.n_lags, h->acc, h->width, h->tiles,
+                                           L.full ? L.nyq_slot : -1, h->lags,
                                            h->t_pushed, S, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "power spectra launch");
   return NFS_OK;

@@ -241,6 +241,8 @@ __device__ __forceinline__ int ring_slot(int n, const int32_t* __restrict__ tile
                                          int kx) {
   const int t = kx >> 3;
   const int R = tiles[(n >> 4) + 1 + t];
+  // R = n/2 marks a tile that keeps all n rows (full half-plane plans).
+  if (R >= (n >> 1)) return tiles[t] + r * 8 + (kx & 7);
   const int ky = r < (n >> 1) ? r : r - n;
   if (ky > R || -ky > R) return -1;
   const int rank = r <= R ? r : r - (n - 2 * R - 1);

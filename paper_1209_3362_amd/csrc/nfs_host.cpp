@@ -52,14 +52,14 @@ nfs_status validate_desc(const nfs_desc* d, std::string* err) {
   if (d->host_staging != 0 && d->host_staging != 1)
     return fail(NFS_E_ARG, "host_staging must be 0 or 1");
   if (d->backward != 0 && d->backward != 1) return fail(NFS_E_ARG, "backward must be 0 or 1");
+  if (d->full_spectra != 0 && d->full_spectra != 1)
+    return fail(NFS_E_ARG, "full_spectra must be 0 or 1");
   if (d->n_lags < 1 || !d->lags) return fail(NFS_E_LAGS, "need at least one lag");
   for (int i = 0; i < d->n_lags; ++i) {
     if (d->lags[i] < 0) return fail(NFS_E_LAGS, "lags must be >= 0");
     if (i && d->lags[i] <= d->lags[i - 1])
       return fail(NFS_E_LAGS, "lags must be strictly increasing");
   }
-  if (d->lags[d->n_lags - 1] > kMaxLag)
-    return fail(NFS_E_LAGS, "largest lag exceeds 2400");
   if (d->n_bins < 1 || d->n_bins > d->n / 2)
     return fail(NFS_E_BINS, "n_bins must be in [1, n/2]");
   if (d->capacity < 0) return fail(NFS_E_CAPACITY, "capacity must be >= 0");
@@ -84,43 +84,58 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.accum = d->accum;
   o.host_staging = d->host_staging;
   o.backward = d->backward;
+  o.full = d->full_spectra;
   o.frame_bytes = size_t(d->n) * d->n * (d->in_dtype == NFS_IN_U16 ? 2 : 4);
   o.mode_bytes = d->spec_dtype == NFS_SPEC_F32 ? 8 : 4;
   o.lags.assign(d->lags, d->lags + d->n_lags);
   o.max_lag = o.lags.back();
 
-  // Stored modes: k_x in [0, n/2), |k| < n/2; row r has k_y = r (r < n/2)
-  // or r - n, and keeps k_x in [0, width).
-  o.row_width.resize(o.n);
+  // Modes in a ring: k_x in [0, n/2), |k| < n/2; row r has k_y = r
+  // (r < n/2) or r - n, and its ring modes are k_x in [0, disc[r]). Plans
+  // store those only, or (full) every k_x in [0, n/2] of every row.
+  std::vector<int32_t> disc(size_t(o.n));
   const int64_t hh = int64_t(o.h) * o.h;
   int64_t acc = 0;
   for (int r = 0; r < o.n; ++r) {
     const int64_t ky = r < o.h ? r : r - o.n;
     const int64_t rem = hh - 1 - ky * ky;
     const int w = rem < 0 ? 0 : int(isqrt_u64(uint64_t(rem))) + 1;
-    o.row_width[r] = w;
+    disc[size_t(r)] = w;
     acc += w;
   }
-  o.modes = acc;
+  o.binned = acc;
+  if (o.full) {
+    o.row_width.assign(size_t(o.n), o.h);
+    o.modes = int64_t(o.n) * (o.h + 1);
+  } else {
+    o.row_width = disc;
+    o.modes = acc;
+  }
   // Slots: tiles of 8 columns, each keeping the rows |k_y| <= R_t with
-  // R_t = isqrt((n/2)^2 - 1 - (8t)^2) (the rows where column 8t is stored).
+  // R_t = isqrt((n/2)^2 - 1 - (8t)^2) (the rows where column 8t is stored);
+  // full plans keep all n rows of every tile (R_t = n/2) and put the
+  // k_x = n/2 column after the tiles, row r in slot nyq_slot + r.
   const int T = o.n / 16;
   o.tiles.assign(size_t(2 * T + 1), 0);
   int64_t base = 0;
   for (int t = 0; t < T; ++t) {
-    const int R = int(isqrt_u64(uint64_t(hh - 1 - int64_t(8 * t) * (8 * t))));
+    const int R = o.full ? o.h : int(isqrt_u64(uint64_t(hh - 1 - int64_t(8 * t) * (8 * t))));
     o.tiles[size_t(t)] = int32_t(base);
     o.tiles[size_t(T + 1 + t)] = R;
-    base += 8 * (2 * int64_t(R) + 1);
+    base += o.full ? 8 * int64_t(o.n) : 8 * (2 * int64_t(R) + 1);
   }
   o.tiles[size_t(T)] = int32_t(base);
+  if (o.full) {
+    o.nyq_slot = base;
+    base += o.n;
+  }
   o.slots = base;
   o.mode_stride = int64_t(align_up(size_t(base), 64));
 
   // Binning table and segments, rings in order. On row k_y the half-plane
   // modes of ring b are the run k_x in [ceil_sqrt(lo - k_y^2),
   // ceil_sqrt(hi - k_y^2)); every one of them is stored (|k| < n/2).
-  o.bin_slots.reserve(size_t(o.modes));
+  o.bin_slots.reserve(size_t(o.binned));
   o.bin_seg0.push_back(0);
   for (int b = 0; b < o.n_bins; ++b) {
     int64_t lo, hi;
@@ -144,10 +159,10 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
     o.bin_seg0.push_back(int32_t(o.seg_first.size()));
   }
   o.seg_first.push_back(int32_t(o.bin_slots.size()));
-  // The rings partition the stored modes: each is listed exactly once.
+  // The rings partition the modes with |k| < n/2: each is listed exactly once.
   {
     std::vector<char> seen(size_t(o.slots), 0);
-    bool ok = int64_t(o.bin_slots.size()) == o.modes;
+    bool ok = int64_t(o.bin_slots.size()) == o.binned;
     for (size_t i = 0; ok && i < o.bin_slots.size(); ++i) {
       const int32_t slot = o.bin_slots[i] >> 1;
       ok = slot >= 0 && slot < o.slots && !seen[size_t(slot)];
@@ -159,14 +174,26 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
     }
   }
 
+  // Delays up to kMaxLag in LDS-history groups of up to 96, longer ones in
+  // groups of up to kGlobalLags for the global-memory kernel.
+  int n_short = 0;
+  while (n_short < o.n_lags && o.lags[size_t(n_short)] <= kMaxLag) ++n_short;
   const int max_group = kMaxLagsPerWave * kMaxPairWaves;
-  for (int first = 0; first < o.n_lags; first += max_group) {
+  for (int first = 0; first < n_short; first += max_group) {
     LagGroup g;
-    const int count = std::min(max_group, o.n_lags - first);
+    const int count = std::min(max_group, n_short - first);
     if (!plan_group(o.lags, first, count, &g)) {
       if (err) *err = "lag group does not fit the pair kernel's history";
       return NFS_E_LAGS;
     }
+    o.groups.push_back(g);
+  }
+  for (int first = n_short; first < o.n_lags; first += kGlobalLags) {
+    LagGroup g;
+    g.first = first;
+    g.count = std::min(kGlobalLags, o.n_lags - first);
+    g.max_lag = o.lags[size_t(first + g.count - 1)];
+    g.modes = 0;
     o.groups.push_back(g);
   }
 
@@ -186,6 +213,7 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_rowsum = take(size_t(o.batch) * o.n * 8);
   // Row sums of |frame - reference|, for the FP16 scale only.
   o.off_rowabs = take(o.spec_dtype == NFS_SPEC_F16 ? size_t(o.batch) * o.n * 8 : 0);
+  o.off_nyq = take(o.full ? size_t(o.batch) * o.n * 4 : 0);
   o.off_acc = take(size_t(o.n_lags) * o.mode_stride * 4);
   const size_t nseg = o.seg_first.size() - 1;
   o.off_segs = take((o.seg_first.size() + o.bin_seg0.size()) * 4);
@@ -216,7 +244,7 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
     const uint64_t nb2 = uint64_t(o.n_bins) * uint64_t(o.n_bins);
     for (int r = 0; r < o.n; ++r) {
       const int64_t ky = r < o.h ? r : r - o.n;
-      for (int kx = 0; kx < o.row_width[r]; ++kx) {
+      for (int kx = 0; kx < disc[size_t(r)]; ++kx) {
         const uint64_t k2 = uint64_t(ky * ky) + uint64_t(kx) * uint64_t(kx);
         const int b = int(isqrt_u64(k2 * nb2) / uint64_t(o.h));
         o.mode_bin[size_t(ring_slot_host(o, r, kx))] = b;
@@ -256,6 +284,7 @@ int ring_slot_host(const Layout& L, int r, int kx) {
   const int T = L.n / 16;
   const int t = kx / 8;
   const int R = L.tiles[size_t(T + 1 + t)];
+  if (R >= L.h) return L.tiles[size_t(t)] + r * 8 + kx % 8;
   const int ky = r < L.h ? r : r - L.n;
   if (ky > R || -ky > R) return -1;
   const int rank = r <= R ? r : r - (L.n - 2 * R - 1);

@@ -52,9 +52,14 @@ struct Layout {
   int host_staging = 0;    // two staging buffers of `batch` frames for host pushes
   size_t frame_bytes = 0;  // bytes of one input frame
   int backward = 0;        // nfs_backward buffers reserved
+  int full = 0;            // every half-plane mode stored (desc.full_spectra)
+  // Full plans: slot of the k_x = n/2 mode of row r is nyq_slot + r (after
+  // the tiles); -1 otherwise.
+  int64_t nyq_slot = -1;
+  int64_t binned = 0;      // modes that land in a ring (every plan bins only these)
   int max_lag = 0;
   std::vector<int32_t> lags;
-  std::vector<int32_t> row_width;   // [n] stored modes of transform-order row r
+  std::vector<int32_t> row_width;   // [n] stored modes k_x < n/2 of transform-order row r
   // Tiled slot layout (see ring_slot): {base_0 .. base_T, R_0 .. R_{T-1}},
   // T = n / 16 tiles of 8 columns.
   std::vector<int32_t> tiles;
@@ -70,6 +75,7 @@ struct Layout {
   size_t off_ring = 0, off_inter = 0, off_rowsum = 0, off_rowabs = 0, off_acc = 0;
   size_t off_status = 0, off_tw = 0, off_width = 0, off_tiles = 0;
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
+  size_t off_nyq = 0;     // full plans: the row pass's k_x = n/2 values [batch][n]
   size_t off_stage = 0;   // host-push staging: 2 x batch frames (host_staging)
   // nfs_backward (backward): k-space gradients of a batch [batch][mode_stride]
   // complex (the same region later holds its g' images [batch][n][n] floats),

@@ -17,9 +17,18 @@ namespace nfs {
 // workgroup transforms), rowsum [nframes][n] and,
 // when rowabs is not null, rowabs [nframes][n]: the rows' sums of |what was
 // transformed|.
+// nyq: [nframes][n] floats receiving X_y(n/2) (full half-plane plans), or null.
 hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* ref,
                            const float* window, int nframes, float2* inter, double* rowsum,
-                           double* rowabs, const float2* tw, hipStream_t s);
+                           double* rowabs, float* nyq, const float2* tw, hipStream_t s);
+
+// Column k_x = n/2 of full half-plane plans, after the column pass of the
+// same frames: transform of nyq[f][y] over y, stored like the other modes
+// (reference: unscaled FP32 into refspec) at slots nyq_slot + r.
+hipError_t launch_nyquist_col(int n, bool reference, int spec, const float* nyq, int nframes,
+                              int64_t t0, int64_t capacity, int64_t mode_stride,
+                              int64_t nyq_slot, const float2* tw, const float4* fscale,
+                              void* ring, float2* refspec, hipStream_t s);
 
 // Column pass (per column k_x: complex transform over the n rows), with the
 // frame scales formed from the row sums.
@@ -94,7 +103,7 @@ hipError_t launch_expand_spectrum(int n, const void* ring, int spec, int64_t slo
 // [n_lags][n][n/2 + 1] (0 at modes that are not stored, NaN for every mode
 // of a delay with n_frames - lag <= 0).
 hipError_t launch_power_spectra(int n, int n_lags, const float* acc, const int32_t* row_width,
-                                const int32_t* tiles, const int32_t* lags,
+                                const int32_t* tiles, int64_t nyq_slot, const int32_t* lags,
                                 int64_t n_frames, float* out, hipStream_t s);
 
 // Differentiation form (nfs_backward). g table: gtab[l][b] =

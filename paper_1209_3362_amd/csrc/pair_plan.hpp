@@ -21,8 +21,11 @@ constexpr int kMaxPairWaves = 12;
 constexpr int kPairMirror = kPairChunk + kMaxLagsPerWave;
 // LDS a workgroup may allocate on gfx950.
 constexpr int kLdsBytes = 160 * 1024;
-// Largest delay the pair kernel's on-chip history supports (K = 8 modes).
+// Largest delay the pair kernel's on-chip history supports (K = 8 modes);
+// groups of longer delays run the global-memory kernel (modes == 0), up to
+// kGlobalLags delays per launch.
 constexpr int kMaxLag = 2400;
+constexpr int kGlobalLags = 8;
 
 // Lags of the busiest SIMD when `count` lags are split over `waves` waves
 // in contiguous slices whose lengths differ by at most one (the first
@@ -34,7 +37,7 @@ struct LagGroup {
   int first = 0;      // index of the group's first lag in the lag list
   int count = 0;      // lags in the group
   int max_lag = 0;    // largest lag of the group
-  int modes = 0;      // K: modes per workgroup
+  int modes = 0;      // K: modes per workgroup; 0: the global-memory kernel
   int hist = 0;       // H: history rows kept in LDS (multiple of the chunk)
   int waves = 0;      // waves that sum lags (the launch has 8, or 12 if more)
   int per_wave = 0;   // most lags of one wave (<= kMaxLagsPerWave)

@@ -429,6 +429,79 @@ hipError_t pair_launch(const char* ring, int spec, const float2* refspec, const 
   return hipGetLastError();
 }
 
+// Long delays, whose history does not fit the LDS ring: one thread per mode
+// (256 consecutive modes per workgroup, loads coalesced across modes),
+// walking the window's targets t in order; the target's value is read
+// once and each lag's older frame t - tau comes from the ring in memory
+// (L2 or HBM), decoded and corrected as the LDS copy does. Up to
+// kGlobalLags lags per launch. KAHAN: each lag's terms of 32 consecutive
+// targets are summed in FP32 and the chunk sums added with Kahan
+// compensation; the running sum minus the compensation is the result.
+template <bool KAHAN>
+__global__ __launch_bounds__(256) void pair_global_kernel(
+    const char* __restrict__ ring, int spec, const float2* __restrict__ refspec,
+    const float4* __restrict__ fscale, int64_t n_modes, int64_t mode_stride, int64_t capacity,
+    int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags,
+    float* __restrict__ acc, int acc_pitch, bool assign) {
+  constexpr int GL = kGlobalLags;
+  const int64_t m = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (m >= n_modes) return;  // no barrier below
+  const bool f32 = spec == kSpecF32;
+  const int64_t mode_bytes = f32 ? 8 : 4;
+  const float2 R = refspec[m];
+  auto value = [&](int64_t slot) -> float2 {
+    const float4 sc = fscale[slot];
+    const char* p = ring + (slot * mode_stride + m) * mode_bytes;
+    float2 a;
+    if (f32) {
+      a = *reinterpret_cast<const float2*>(p);
+    } else {
+      const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+      a = spec == kSpecBF16 ? unpack_bf16(w) : unpack_f16(w);
+      a = make_float2(a.x * sc.z, a.y * sc.z);
+    }
+    return make_float2(fmaf(sc.y, R.x, a.x), fmaf(sc.y, R.y, a.y));
+  };
+  int tau[GL];
+#pragma unroll
+  for (int s = 0; s < GL; ++s) tau[s] = __builtin_amdgcn_readfirstlane(s < n_lags ? lags[s] : 0);
+  float run[GL], comp[GL], part[GL];
+#pragma unroll
+  for (int s = 0; s < GL; ++s) run[s] = comp[s] = part[s] = 0.f;
+  int64_t slot = T0 % capacity;
+  for (int64_t t = T0; t < T1; ++t) {
+    const float2 at = value(slot);
+#pragma unroll
+    for (int s = 0; s < GL; ++s) {
+      if (s < n_lags && t >= tau[s]) {
+        const int64_t so = slot >= tau[s] ? slot - tau[s] : slot - tau[s] + capacity;
+        const float2 o = value(so);
+        const float dx = at.x - o.x, dy = at.y - o.y;
+        part[s] = fmaf(dx, dx, fmaf(dy, dy, part[s]));
+      }
+    }
+    if (KAHAN && ((t - T0) % 32 == 31 || t + 1 == T1)) {
+#pragma unroll
+      for (int s = 0; s < GL; ++s) {
+        const float y = part[s] - comp[s];
+        const float z = run[s] + y;
+        comp[s] = (z - run[s]) - y;
+        run[s] = z;
+        part[s] = 0.f;
+      }
+    }
+    if (++slot == capacity) slot = 0;
+  }
+#pragma unroll
+  for (int s = 0; s < GL; ++s) {
+    if (s < n_lags) {
+      const float total = KAHAN ? run[s] - comp[s] : part[s];
+      float* dst = acc + m * acc_pitch + s;
+      *dst = assign ? total : *dst + total;
+    }
+  }
+}
+
 // Up to 8 lag waves run in 8-wave workgroups; more (only with 6 or more
 // lags per wave) in 12-wave ones.
 template <int K, bool KAHAN>
@@ -475,6 +548,19 @@ hipError_t launch_pairs(const void* ring, int spec, bool kahan, const float2* re
                         int modes, int hist, int waves, int per_wave, size_t lds,
                         hipStream_t s) {
   const char* r = static_cast<const char*>(ring);
+  if (modes == 0) {  // the global-memory kernel (long delays)
+    if (n_lags < 1 || n_lags > kGlobalLags) return hipErrorInvalidValue;
+    const dim3 grid(unsigned((n_modes + 255) / 256));
+    if (kahan)
+      hipLaunchKernelGGL(pair_global_kernel<true>, grid, dim3(256), 0, s, r, spec, refspec,
+                         fscale, n_modes, mode_stride, capacity, T0, T1, lags, n_lags, acc,
+                         acc_pitch, assign);
+    else
+      hipLaunchKernelGGL(pair_global_kernel<false>, grid, dim3(256), 0, s, r, spec, refspec,
+                         fscale, n_modes, mode_stride, capacity, T0, T1, lags, n_lags, acc,
+                         acc_pitch, assign);
+    return hipGetLastError();
+  }
 #define NFS_PAIR_CASE(KK, KH)                                                              \
   return pair_dispatch<KK, KH>(per_wave, r, spec, refspec, fscale, n_modes, mode_stride,  \
                                capacity, T0, T1, lags, n_lags, max_lag, acc, acc_pitch,   \

@@ -47,6 +47,7 @@ class NfsDesc(ctypes.Structure):
         ("window", ctypes.c_void_p),
         ("host_staging", ctypes.c_int32),
         ("backward", ctypes.c_int32),
+        ("full_spectra", ctypes.c_int32),
     ]
 
 
@@ -112,22 +113,22 @@ def load_library():
 
 
 def _desc(n, lags, n_bins, in_dtype, capacity, window_ptr, spec="f32", accum="plain",
-          host_staging=False, backward=False):
+          host_staging=False, backward=False, full_spectra=False):
     arr = (ctypes.c_int32 * len(lags))(*[int(t) for t in lags])
     d = NfsDesc(n=int(n), in_dtype=IN_DTYPES[in_dtype], spec_dtype=SPEC_DTYPES[spec],
                 accum=ACCUMS[accum],
                 n_lags=len(lags), lags=arr, n_bins=int(n_bins),
                 capacity=int(capacity), window=window_ptr, host_staging=int(host_staging),
-                backward=int(backward))
+                backward=int(backward), full_spectra=int(full_spectra))
     return d, arr
 
 
 def workspace_size(n, lags, n_bins, in_dtype="u16", capacity=0, window=False, spec="f32",
-                   accum="plain", host_staging=False, backward=False):
+                   accum="plain", host_staging=False, backward=False, full_spectra=False):
     """Workspace bytes for a plan (host only; raises NfsError on a bad desc)."""
     lib = load_library()
     d, _keep = _desc(n, lags, n_bins, in_dtype, capacity, 1 if window else None, spec, accum,
-                     host_staging, backward)
+                     host_staging, backward, full_spectra)
     out = ctypes.c_size_t(0)
     st = lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out))
     if st != NFS_OK:
@@ -187,7 +188,7 @@ class Plan:
 
     Plan(n, lags, n_bins, in_dtype="u16"|"f32", capacity=N, window=None,
          spec="f32"|"bf16"|"f16", accum="plain"|"kahan", host_staging=False,
-         backward=False)
+         backward=False, full_spectra=False)
     .push(frames)            frames: [count][n][n] uint16/float32 on the device, or in
                              host memory (pinned for overlap) with host_staging=True
     .structure_function()    -> (D float64 [L][n_bins], counts int64 [n_bins],
@@ -197,7 +198,7 @@ class Plan:
 
     def __init__(self, n, lags, n_bins, in_dtype="u16", capacity=0, window=None,
                  device=None, stream=None, spec="f32", accum="plain", host_staging=False,
-                 backward=False):
+                 backward=False, full_spectra=False):
         self.lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the structure-function library needs one")
@@ -219,7 +220,7 @@ class Plan:
         self._borrowed = []  # host frames the copy stream may still read
         self.pushed = 0      # frames pushed since the plan was made or reset
         d, self._lags_keep = _desc(self.n, self.lags, self.n_bins, in_dtype, capacity, wptr,
-                                   spec, accum, self.host_staging, backward)
+                                   spec, accum, self.host_staging, backward, full_spectra)
         size = ctypes.c_size_t(0)
         st = self.lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(size))
         self._check(st, None)
@@ -306,7 +307,9 @@ class Plan:
         return D, counts, pairs, status
 
     def power_spectra(self, sync=True):
-        """P_tau(k) as float32 [n_lags][n][n/2 + 1] (nfs_power_spectra_2d)."""
+        """P_tau(k) as float32 [n_lags][n][n/2 + 1] (nfs_power_spectra_2d):
+        every mode for a plan made with full_spectra=True, else the modes
+        that land in a ring and 0 elsewhere."""
         out = torch.empty((len(self.lags), self.n, self.n // 2 + 1), dtype=torch.float32,
                           device=self.device)
         self._check(self.lib.nfs_power_spectra_2d(self.handle, _ptr(out)))

@@ -96,8 +96,10 @@ def test_descriptor_validation():
     assert code(lags=[2, 1]) == "NFS_E_LAGS"
     assert code(lags=[1, 1]) == "NFS_E_LAGS"
     assert code(lags=[-1, 3]) == "NFS_E_LAGS"
-    assert code(lags=[1, 2401], capacity=3000) == "NFS_E_LAGS"
+    # Delays beyond the pair kernel's LDS history take its global-memory form.
+    assert code(lags=[1, 2401], capacity=3000) == "NFS_OK"
     assert code(lags=[1, 2400], capacity=3000) == "NFS_OK"
+    assert code(lags=[1, 2, 100000], capacity=100001) == "NFS_OK"
     assert code(n_bins=0) == "NFS_E_BINS"
     assert code(n_bins=65) == "NFS_E_BINS"
     assert code(n_bins=64) == "NFS_OK"
@@ -298,3 +300,18 @@ def test_noalloc_checks_size_and_arguments_on_the_host():
     assert nfs.status_name(lib.nfs_structure_function_noalloc(
         ctypes.byref(bad), ctypes.c_void_p(16), 1, ctypes.c_void_p(16), None, None, None,
         None)) == "NFS_E_SIZE"
+
+
+def test_full_spectra_layout():
+    """desc.full_spectra = 1 stores every half-plane mode: n (n/2 + 1) modes
+    in all-row tiles plus the k_x = n/2 column; other values are refused."""
+    lib = nfs.load_library()
+    for n in (16, 128, 1024):
+        small = nfs.workspace_size(n, [1, 2], n // 2, capacity=8)
+        full = nfs.workspace_size(n, [1, 2], n // 2, capacity=8, full_spectra=True)
+        assert full > small
+    d, _keep = nfs.nfs._desc(128, [1, 2], 64, "f32", 8, None, full_spectra=True)
+    d.full_spectra = 2
+    out = ctypes.c_size_t(0)
+    assert nfs.status_name(lib.nfs_plan_workspace_size(ctypes.byref(d), ctypes.byref(out))) \
+        == "NFS_E_ARG"

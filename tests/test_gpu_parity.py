@@ -275,6 +275,38 @@ def test_long_lags_use_narrow_tiles(lags):
     assert_D_close(D, ref["D"], rtol=1e-4)
 
 
+@pytest.mark.parametrize("capacity,accum,chunk", [(4001, "plain", None), (3100, "plain", 333),
+                                                  (4001, "kahan", 1000)])
+def test_lags_beyond_the_lds_history(capacity, accum, chunk):
+    """Delays above 2400 frames (the LDS history's limit) run the
+    global-memory pair kernel: with the whole stack resident (delays up to
+    one without a pair), with a ring shorter than the stack (sums flushed
+    per window) and with Kahan sums."""
+    n, N = 16, 4000
+    lags = [1, 5, 700, 2401, 3000] + ([3999, 4000] if capacity > 4000 else [])
+    cfg = gen.config("c1", n=n, N=N, n_bins=8)
+    say(f"lags beyond 2400: {lags}, N={N}, 16x16, ring {capacity}, {accum}, chunk {chunk}")
+    f = gen.make_stack(cfg, 12)
+    ref = oracle.structure_function(f.numpy(), lags, 8)
+    D, C, P, st = run_plan(f, lags, 8, "f32", capacity=capacity, chunk=chunk, accum=accum)
+    assert st == 0 and np.array_equal(P, ref["pairs"])
+    assert_D_close(D, ref["D"], rtol=1e-4)
+
+
+def test_short_and_long_lag_groups():
+    """99 short delays (two LDS-history launches) and 10 long ones (two
+    global-memory launches of 8 and 2) in one plan."""
+    n, N = 16, 3000
+    lags = list(range(0, 99)) + [2450 + 50 * i for i in range(10)]
+    cfg = gen.config("c1", n=n, N=N, n_bins=8)
+    say(f"99 short + 10 long lags, N={N}, 16x16")
+    f = gen.make_stack(cfg, 13)
+    ref = oracle.structure_function(f.numpy(), lags, 8)
+    D, C, P, st = run_plan(f, lags, 8, "f32")
+    assert np.array_equal(P, ref["pairs"])
+    assert_D_close(D, ref["D"], rtol=1e-4)
+
+
 def test_more_lags_than_one_launch():
     n, N = 32, 260
     lags = list(range(0, 200))
