@@ -178,6 +178,15 @@ nfs_status nfs_push_host_frames(nfs_handle h, const void* frames, int64_t count)
  * over different lanes), not bit for bit. */
 nfs_status nfs_tune_pairs(nfs_handle h, int32_t* choices, int32_t* groups);
 
+/* Apply pair-kernel launch shapes chosen earlier (by nfs_tune_pairs on a
+ * plan of the same frame size, lags and storage, e.g. kept in a cache):
+ * choices: host int32 [2 * groups] of (modes, waves) per lag group, in the
+ * order nfs_tune_pairs reports them. Every pair must be a shape the kernel
+ * supports for that group ((0, 0) for a group of delays beyond the LDS
+ * history), and groups must equal the plan's group count, else NFS_E_ARG
+ * and the plan is unchanged. Host only; enqueues nothing. */
+nfs_status nfs_set_pair_shapes(nfs_handle h, const int32_t* choices, int32_t groups);
+
 /* Accumulate the pair sums of every frame pushed so far (enqueued). Needed
  * only to split the work, e.g. to overlap it with acquisition or to time it:
  * nfs_structure_function does it implicitly. */
@@ -313,6 +322,19 @@ const char* nfs_status_string(nfs_status s);
 /* Description of the last error on this handle ("" if none); valid until
  * the next call on the handle. */
 const char* nfs_last_error(nfs_handle h);
+
+/* Work counters of the plan since it was made or last reset, copied to
+ * the device buffer `counters`, int64 [2] (enqueued on the plan's stream):
+ *   [0] frames transformed (one per pushed frame; a backward that
+ *       recomputes spectra adds one per frame it transforms again);
+ *   [1] (target, lag) frame pairs whose terms the pair kernels summed, as
+ *       counted by those kernels from their own loop decisions; after
+ *       nfs_structure_function this equals sum over the lags of
+ *       max(0, N - tau) (the processing section's count of differences per
+ *       delay), N the frames pushed.
+ * Pairs still pending (pushed frames whose sums nfs_accumulate or
+ * nfs_structure_function has not yet enqueued) are not counted. */
+nfs_status nfs_work_counters(nfs_handle h, int64_t* counters);
 
 /* Allocation-free form, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -312,7 +312,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
     float4* __restrict__ fscale, int32_t* __restrict__ status, int nframes, int per_group,
     int64_t t0, int64_t capacity, int64_t mode_stride, int64_t n_modes,
     const int32_t* __restrict__ tiles, const float2* __restrict__ tw, char* __restrict__ ring,
-    float2* __restrict__ refspec) {
+    float2* __restrict__ refspec, unsigned long long* __restrict__ work) {
   static_assert(!REF || SPEC == kSpecF32, "the reference transform is kept in FP32");
   constexpr bool F16 = SPEC == kSpecF16;
   constexpr uint32_t MODE_BYTES = SPEC == kSpecF32 ? 8u : 4u;
@@ -432,6 +432,7 @@ __global__ __launch_bounds__(ColCfg<N>::THREADS, ColCfg<N>::MINW) void col_pass_
         fscale[slot] =
             make_float4(float(sigma), float(sigma - sigma_ref), float(ldexp(1.0, -e)), 0.f);
         if (bad) atomicOr(status, 1);
+        if (work) atomicAdd(work, 1ull);  // work counter: frames transformed
       }
     }
     const BufferRsrc dst =
@@ -567,7 +568,8 @@ hipError_t col_launch(bool reference, int spec, const float2* inter, const doubl
                       const double* rowabs, int nframes, int64_t t0, int64_t capacity,
                       int64_t mode_stride, int64_t n_modes, const int32_t* tiles,
                       const float2* tw, void* ring, float2* refspec,
-                      double* refscal, float4* fscale, int32_t* status, hipStream_t s) {
+                      double* refscal, float4* fscale, int32_t* status,
+                      unsigned long long* work, hipStream_t s) {
   using C = ColCfg<N>;
   const int per = frames_per_group(nframes, C::GROUPS);
   const int64_t blocks = int64_t(C::GROUPS) * ((nframes + per - 1) / per);
@@ -576,7 +578,7 @@ hipError_t col_launch(bool reference, int spec, const float2* inter, const doubl
   hipLaunchKernelGGL((col_pass_kernel<N, REFV, SPECV>), dim3(unsigned(blocks)),               \
                      dim3(C::THREADS), 0, s, inter, rowsum, rowabs, refscal, fscale, status,   \
                      nframes, per, t0, capacity, mode_stride, n_modes, tiles, tw, ringb,     \
-                     refspec)
+                     refspec, work)
   if (reference) {
     hipLaunchKernelGGL(ref_scale_kernel, dim3(1), dim3(256), 0, s, N, rowsum, refscal, status);
     NFS_COL_GO(true, kSpecF32);
@@ -643,12 +645,12 @@ hipError_t launch_col_pass(int n, bool reference, int spec, const float2* inter,
                            int64_t capacity, int64_t mode_stride, int64_t n_modes,
                            const int32_t* tiles, const float2* tw, void* ring,
                            float2* refspec, double* refscal, float4* fscale, int32_t* status,
-                           hipStream_t s) {
+                           unsigned long long* work, hipStream_t s) {
 #define NFS_COL_CASE(NN)                                                                   \
   case NN:                                                                                 \
     return col_launch<NN>(reference, spec, inter, rowsum, rowabs, nframes, t0, capacity,  \
                           mode_stride, n_modes, tiles, tw, ring, refspec,                 \
-                          refscal, fscale, status, s);
+                          refscal, fscale, status, work, s);
   switch (n) {
     NFS_COL_CASE(16)
     NFS_COL_CASE(32)

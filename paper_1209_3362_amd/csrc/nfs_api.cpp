@@ -31,7 +31,10 @@ struct nfs_plan_s {
   double* rowabs = nullptr;     // row sums of |frame - reference| (FP16 storage)
   float* nyq = nullptr;         // full plans: the row pass's k_x = n/2 values
   float* acc = nullptr;
+  float* comp = nullptr;        // Kahan plans: compensation of acc across windows
   int32_t* status = nullptr;    // bit 0: a degenerate frame was pushed
+  // Work counters: {frames transformed, (target, lag) pairs summed}.
+  unsigned long long* work = nullptr;
   double* refscal = nullptr;    // {S_ref, sigma_ref} of the reference frame
   void* ref = nullptr;          // reference frame: first frame of the sequence
   float2* refspec = nullptr;    // its transform on the stored modes
@@ -114,7 +117,8 @@ nfs_status flush_pairs(nfs_plan_s* h) {
                                      L.capacity, h->t_done,
                                      h->t_pushed, h->lags + g.first, g.count, g.max_lag,
                                      h->acc + g.first, L.n_lags, h->sums_fresh, g.modes,
-                                     g.hist, g.waves, g.per_wave, g.lds, h->stream);
+                                     g.hist, g.waves, g.per_wave, g.lds, h->work + 1,
+                                     h->comp ? h->comp + g.first : nullptr, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "pair kernel launch");
   }
   h->sums_fresh = false;
@@ -129,13 +133,17 @@ nfs_status finish_sums(nfs_plan_s* h) {
   if (st != NFS_OK || !h->sums_fresh) return st;
   const nfs::Layout& L = h->L;
   hipError_t e = nfs::launch_fill_u32(h->acc, size_t(L.n_lags) * L.mode_stride, 0u, h->stream);
+  if (e == hipSuccess && h->comp)
+    e = nfs::launch_fill_u32(h->comp, size_t(L.n_lags) * L.mode_stride, 0u, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "fill kernel launch");
   h->sums_fresh = false;
   return NFS_OK;
 }
 
 nfs_status clear_sums(nfs_plan_s* h) {
-  hipError_t e = nfs::launch_fill_u32(h->status, 1, 0u, h->stream);
+  // The status word, the reference scalars (rewritten by the next push) and
+  // the work counters: the first 80 bytes of the status block.
+  hipError_t e = nfs::launch_fill_u32(h->status, 20, 0u, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "fill kernel launch");
   h->sums_fresh = true;
   h->t_pushed = 0;
@@ -172,7 +180,7 @@ nfs_status transform_into_ring(nfs_plan_s* h, const char* src, int64_t b, int64_
   if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
   e = nfs::launch_col_pass(L.n, false, L.spec_dtype, h->inter, h->rowsum, h->rowabs, int(b), t,
                            L.capacity, L.mode_stride, L.slots, h->tiles, h->tw, h->ring,
-                           h->refspec, h->refscal, h->fscale, h->status, h->stream);
+                           h->refspec, h->refscal, h->fscale, h->status, h->work, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "column pass launch");
   if (L.full) {
     e = nfs::launch_nyquist_col(L.n, false, L.spec_dtype, h->nyq, int(b), t, L.capacity,
@@ -201,7 +209,7 @@ nfs_status transform_batch(nfs_plan_s* h, const char* src, int64_t b) {
       e = nfs::launch_col_pass(L.n, true, NFS_SPEC_F32, h->inter, h->rowsum, nullptr, 1, 0,
                                L.capacity, L.mode_stride, L.slots, h->tiles, h->tw,
                                h->ring, h->refspec, h->refscal, h->fscale, h->status,
-                               h->stream);
+                               nullptr, h->stream);
     if (e == hipSuccess && L.full)
       e = nfs::launch_nyquist_col(L.n, true, NFS_SPEC_F32, h->nyq, 1, 0, L.capacity,
                                   L.mode_stride, L.nyq_slot, h->tw, h->fscale, h->ring,
@@ -274,7 +282,9 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
                                             : nullptr;
   h->nyq = L.full ? reinterpret_cast<float*>(h->ws + L.off_nyq) : nullptr;
   h->acc = reinterpret_cast<float*>(h->ws + L.off_acc);
+  h->comp = L.accum == NFS_ACC_KAHAN ? reinterpret_cast<float*>(h->ws + L.off_comp) : nullptr;
   h->status = reinterpret_cast<int32_t*>(h->ws + L.off_status);
+  h->work = reinterpret_cast<unsigned long long*>(h->ws + L.off_status + 64);
   h->tw = reinterpret_cast<float2*>(h->ws + L.off_tw);
   h->width = reinterpret_cast<int32_t*>(h->ws + L.off_width);
   h->tiles = reinterpret_cast<int32_t*>(h->ws + L.off_tiles);
@@ -444,7 +454,7 @@ nfs_status nfs_tune_pairs(nfs_handle h, int32_t* choices, int32_t* groups) {
                                  h->fscale, slots, L.mode_stride, L.capacity, T0, T1,
                                  h->lags + c.first, c.count, c.max_lag, scratch + c.first,
                                  L.n_lags, true, c.modes, c.hist, c.waves, c.per_wave, c.lds,
-                                 h->stream);
+                                 nullptr, nullptr, h->stream);
       };
       e = go();  // warm-up
       if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
@@ -470,6 +480,34 @@ nfs_status nfs_tune_pairs(nfs_handle h, int32_t* choices, int32_t* groups) {
       choices[2 * gi] = h->groups[gi].modes;
       choices[2 * gi + 1] = h->groups[gi].waves;
     }
+  return NFS_OK;
+}
+
+nfs_status nfs_set_pair_shapes(nfs_handle h, const int32_t* choices, int32_t groups) {
+  if (!is_live(h)) return NFS_E_STATE;
+  if (!choices) return fail(h, NFS_E_ARG, "choices is NULL");
+  if (groups != int32_t(h->groups.size()))
+    return fail(h, NFS_E_ARG, "group count differs from the plan's");
+  const nfs::Layout& L = h->L;
+  std::vector<nfs::LagGroup> next = h->groups;
+  for (size_t gi = 0; gi < next.size(); ++gi) {
+    const int modes = choices[2 * gi], waves = choices[2 * gi + 1];
+    const nfs::LagGroup& cur = h->groups[gi];
+    if (cur.modes == 0) {
+      if (modes != 0 || waves != 0)
+        return fail(h, NFS_E_ARG, "a long-delay group has one kernel shape (0, 0)");
+      continue;
+    }
+    bool found = false;
+    for (const nfs::LagGroup& c : nfs::group_candidates(L.lags, cur.first, cur.count))
+      if (c.modes == modes && c.waves == waves) {
+        next[gi] = c;
+        found = true;
+        break;
+      }
+    if (!found) return fail(h, NFS_E_ARG, "shape not supported for this lag group");
+  }
+  h->groups = next;
   return NFS_OK;
 }
 
@@ -600,6 +638,15 @@ nfs_status nfs_structure_function_noalloc(const nfs_desc* desc, const void* fram
   // no stream or event, so the handle can go before the stream passes.
   nfs_status st_destroy = nfs_destroy(h);
   return st != NFS_OK ? st : st_destroy;
+}
+
+nfs_status nfs_work_counters(nfs_handle h, int64_t* counters) {
+  if (!is_live(h)) return NFS_E_STATE;
+  if (!counters) return fail(h, NFS_E_ARG, "counters is NULL");
+  hipError_t e = hipMemcpyAsync(counters, h->work, 2 * sizeof(int64_t),
+                                hipMemcpyDeviceToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "work counter copy");
+  return NFS_OK;
 }
 
 nfs_status nfs_reset(nfs_handle h) {

@@ -215,6 +215,7 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_rowabs = take(o.spec_dtype == NFS_SPEC_F16 ? size_t(o.batch) * o.n * 8 : 0);
   o.off_nyq = take(o.full ? size_t(o.batch) * o.n * 4 : 0);
   o.off_acc = take(size_t(o.n_lags) * o.mode_stride * 4);
+  o.off_comp = take(o.accum == NFS_ACC_KAHAN ? size_t(o.n_lags) * o.mode_stride * 4 : 0);
   const size_t nseg = o.seg_first.size() - 1;
   o.off_segs = take((o.seg_first.size() + o.bin_seg0.size()) * 4);
   o.off_bin_slots = take(o.bin_slots.size() * 4);

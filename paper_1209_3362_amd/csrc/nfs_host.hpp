@@ -76,6 +76,7 @@ struct Layout {
   size_t off_status = 0, off_tw = 0, off_width = 0, off_tiles = 0;
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
   size_t off_nyq = 0;     // full plans: the row pass's k_x = n/2 values [batch][n]
+  size_t off_comp = 0;    // Kahan plans: compensation of the sums, laid out like them
   size_t off_stage = 0;   // host-push staging: 2 x batch frames (host_staging)
   // nfs_backward (backward): k-space gradients of a batch [batch][mode_stride]
   // complex (the same region later holds its g' images [batch][n][n] floats),

@@ -49,7 +49,7 @@ hipError_t launch_col_pass(int n, bool reference, int spec, const float2* inter,
                            int64_t capacity, int64_t mode_stride, int64_t n_modes,
                            const int32_t* tiles, const float2* tw, void* ring,
                            float2* refspec, double* refscal, float4* fscale, int32_t* status,
-                           hipStream_t s);
+                           unsigned long long* work, hipStream_t s);
 
 // Lag-pair accumulation for target frames [T0, T1) and the lags
 // lags[0..n_lags): acc[m * acc_pitch + l] += sum_t |I_t(m) - I_{t - lags[l]}(m)|^2
@@ -60,13 +60,17 @@ hipError_t launch_col_pass(int n, bool reference, int spec, const float2* inter,
 // FP16 ones scaled by 1 / fscale[slot].z). Frames [max(0, T0 - max lag), T1)
 // must be in the ring. `modes` per workgroup (16 or 8), `hist` LDS rows;
 // wave w sums lags of a near-equal contiguous slice (at most per_wave);
-// kahan: chunk sums added with Kahan compensation.
+// modes 0: the global-memory kernel (at most kGlobalLags lags, any delay);
+// kahan: chunk sums added with Kahan compensation, and with comp (laid out
+// like acc) not null the window's totals are added to acc with Kahan
+// compensation kept in comp across launches (assign clears it). work (or
+// null): the (target, lag) pairs summed are added to *work.
 hipError_t launch_pairs(const void* ring, int spec, bool kahan, const float2* refspec,
                         const float4* fscale, int64_t n_modes, int64_t mode_stride,
                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                         int n_lags, int max_lag, float* acc, int acc_pitch, bool assign,
                         int modes, int hist, int waves, int per_wave, size_t lds,
-                        hipStream_t s);
+                        unsigned long long* work, float* comp, hipStream_t s);
 
 // Azimuthal binning from the sums acc [slots][n_lags] (mode-major): segment
 // partials over the binning table bin_slots (entries 2 * slot + (k_x > 0),

@@ -33,6 +33,23 @@ using dev::kSpecF32;
 using dev::unpack_bf16;
 using dev::unpack_f16;
 
+// Window total v of one (mode, lag) into the running sum: stored (and the
+// compensation cleared) for the first window after a reset, else added
+// with Kahan compensation kept in comp across windows, so long streams
+// summed in many ring windows keep the compensated accuracy.
+__device__ __forceinline__ void kahan_window_add(float* sum, float* comp, float v, bool assign) {
+  if (assign) {
+    *sum = v;
+    *comp = 0.f;
+    return;
+  }
+  const float c = *comp, a = *sum;
+  const float y = v - c;
+  const float t = a + y;
+  *comp = (t - a) - y;
+  *sum = t;
+}
+
 // K modes per workgroup, MAXLW lag slots per wave, NW waves launched: the
 // lag list is split into lag_waves <= NW contiguous slices of near-equal
 // length, one per wave; slots past a slice's end read harmless rows and are
@@ -46,7 +63,8 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
     const char* __restrict__ ring, int spec, const float2* __restrict__ refspec,
     const float4* __restrict__ fscale, int64_t n_modes, int64_t mode_stride, int64_t capacity,
     int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags, int max_lag,
-    float* __restrict__ acc, int acc_pitch, bool assign, int H, int lag_waves) {
+    float* __restrict__ acc, int acc_pitch, bool assign, int H, int lag_waves,
+    unsigned long long* __restrict__ work, float* __restrict__ comp) {
   static_assert(K == 16 || K == 8, "16 or 8 modes per workgroup");
   constexpr int S = kPairChunk;  // frames per chunk
   constexpr int G = 64 / K;         // lanes sharing one mode inside a wave
@@ -237,6 +255,9 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
 #pragma unroll
   for (int s = 0; s < MAXLW; ++s)
     if (s < l_count) first_max = max(first_max, first[s]);
+  // Work counter: (target, lag) pairs this wave sums, counted from the same
+  // wave-uniform decisions that select the sums (scalar registers).
+  uint64_t npairs = 0;
 
   // Lane (m, g) reads rows r + g * RPT + i of column m for a ring row r.
   const float2* lane_hist = hist + g * RPT * K + m;
@@ -286,11 +307,13 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
       if (s < l_count) {
         if (full && c >= first[s]) {
           acc_plain(cur, o, s);
+          npairs += S;
         } else if (c + S > first[s]) {
           // Targets [lo, hi) of the chunk have partners. When both ends fall
           // on lane boundaries every lane's run is wholly in or out: plain
           // sums on the lanes that are in; otherwise per-target selects.
           const int lo = max(first[s] - c, 0), hi = min(len - c, S);
+          npairs += hi > lo ? uint64_t(hi - lo) : 0;
           if (lo % RPT == 0 && hi % RPT == 0) {
             if (g * RPT >= lo && g * RPT < hi) acc_plain(cur, o, s);
           } else {
@@ -372,20 +395,27 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
   if (l_count == MAXLW && consecutive) {
     for (; c < lenS; c += S)
       chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LMax{}, Yes{}, cur, rows); });
+    npairs += uint64_t(MAXLW * S) * uint64_t((lenS - ca) / S);
   } else if (l_count == MAXLW) {
     for (; c < lenS; c += S)
       chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LMax{}, No{}, cur, rows); });
+    npairs += uint64_t(MAXLW * S) * uint64_t((lenS - ca) / S);
   } else if (MAXLW > 1 && l_count == LS && consecutive) {
     for (; c < lenS; c += S)
       chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LLess{}, Yes{}, cur, rows); });
+    npairs += uint64_t(LS * S) * uint64_t((lenS - ca) / S);
   } else if (MAXLW > 1 && l_count == LS) {
     for (; c < lenS; c += S)
       chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LLess{}, No{}, cur, rows); });
+    npairs += uint64_t(LS * S) * uint64_t((lenS - ca) / S);
   } else {
     // Waves without lags only copy rows.
     for (; c < lenS; c += S) chunk(c, [](int, const float2*, auto&&) {});
   }
   for (; c < len; c += S) chunk(c, generic);
+
+  if (work && blockIdx.x == 0 && lane == 0 && l_count > 0)
+    atomicAdd(work, static_cast<unsigned long long>(npairs));
 
   // Lanes g = 0..G-1 of one mode hold partial sums over disjoint frames;
   // their total goes through LDS so the workgroup adds its K x n_lags block
@@ -407,8 +437,11 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
   const int nel = int(kmax) * n_lags;
   for (int e = threadIdx.x; e < nel; e += nthreads) {
     const int mm = e / n_lags, l = e - mm * n_lags;
-    float* dst = acc + (m0 + mm) * acc_pitch + l;
-    *dst = assign ? blk[e] : *dst + blk[e];
+    const int64_t at = (m0 + mm) * acc_pitch + l;
+    if (KAHAN && comp)
+      kahan_window_add(acc + at, comp + at, blk[e], assign);
+    else
+      acc[at] = assign ? blk[e] : acc[at] + blk[e];
   }
 }
 
@@ -417,7 +450,7 @@ hipError_t pair_launch(const char* ring, int spec, const float2* refspec, const 
                        int64_t n_modes, int64_t mode_stride, int64_t capacity, int64_t T0,
                        int64_t T1, const int32_t* lags, int n_lags, int max_lag, float* acc,
                        int acc_pitch, bool assign, int hist, int waves, size_t lds,
-                       hipStream_t s) {
+                       unsigned long long* work, float* comp, hipStream_t s) {
   // Allow the LDS history beyond the default dynamic limit; a failure here
   // shows up as a launch error below.
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&pair_kernel<K, P, NW, KAHAN>),
@@ -425,7 +458,7 @@ hipError_t pair_launch(const char* ring, int spec, const float2* refspec, const 
   const int64_t blocks = (n_modes + K - 1) / K;
   hipLaunchKernelGGL((pair_kernel<K, P, NW, KAHAN>), dim3(unsigned(blocks)), dim3(64 * NW), lds,
                      s, ring, spec, refspec, fscale, n_modes, mode_stride, capacity, T0, T1,
-                     lags, n_lags, max_lag, acc, acc_pitch, assign, hist, waves);
+                     lags, n_lags, max_lag, acc, acc_pitch, assign, hist, waves, work, comp);
   return hipGetLastError();
 }
 
@@ -442,7 +475,8 @@ __global__ __launch_bounds__(256) void pair_global_kernel(
     const char* __restrict__ ring, int spec, const float2* __restrict__ refspec,
     const float4* __restrict__ fscale, int64_t n_modes, int64_t mode_stride, int64_t capacity,
     int64_t T0, int64_t T1, const int32_t* __restrict__ lags, int n_lags,
-    float* __restrict__ acc, int acc_pitch, bool assign) {
+    float* __restrict__ acc, int acc_pitch, bool assign, unsigned long long* __restrict__ work,
+    float* __restrict__ comp) {
   constexpr int GL = kGlobalLags;
   const int64_t m = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (m >= n_modes) return;  // no barrier below
@@ -465,10 +499,11 @@ __global__ __launch_bounds__(256) void pair_global_kernel(
   int tau[GL];
 #pragma unroll
   for (int s = 0; s < GL; ++s) tau[s] = __builtin_amdgcn_readfirstlane(s < n_lags ? lags[s] : 0);
-  float run[GL], comp[GL], part[GL];
+  float run[GL], cmp[GL], part[GL];
 #pragma unroll
-  for (int s = 0; s < GL; ++s) run[s] = comp[s] = part[s] = 0.f;
+  for (int s = 0; s < GL; ++s) run[s] = cmp[s] = part[s] = 0.f;
   int64_t slot = T0 % capacity;
+  uint64_t npairs = 0;  // work counter: (target, lag) pairs summed
   for (int64_t t = T0; t < T1; ++t) {
     const float2 at = value(slot);
 #pragma unroll
@@ -478,26 +513,31 @@ __global__ __launch_bounds__(256) void pair_global_kernel(
         const float2 o = value(so);
         const float dx = at.x - o.x, dy = at.y - o.y;
         part[s] = fmaf(dx, dx, fmaf(dy, dy, part[s]));
+        ++npairs;
       }
     }
     if (KAHAN && ((t - T0) % 32 == 31 || t + 1 == T1)) {
 #pragma unroll
       for (int s = 0; s < GL; ++s) {
-        const float y = part[s] - comp[s];
+        const float y = part[s] - cmp[s];
         const float z = run[s] + y;
-        comp[s] = (z - run[s]) - y;
+        cmp[s] = (z - run[s]) - y;
         run[s] = z;
         part[s] = 0.f;
       }
     }
     if (++slot == capacity) slot = 0;
   }
+  if (work && m == 0) atomicAdd(work, static_cast<unsigned long long>(npairs));
 #pragma unroll
   for (int s = 0; s < GL; ++s) {
     if (s < n_lags) {
-      const float total = KAHAN ? run[s] - comp[s] : part[s];
-      float* dst = acc + m * acc_pitch + s;
-      *dst = assign ? total : *dst + total;
+      const float total = KAHAN ? run[s] - cmp[s] : part[s];
+      const int64_t at = m * acc_pitch + s;
+      if (KAHAN && comp)
+        kahan_window_add(acc + at, comp + at, total, assign);
+      else
+        acc[at] = assign ? total : acc[at] + total;
     }
   }
 }
@@ -509,11 +549,12 @@ hipError_t pair_dispatch(int per_wave, const char* ring, int spec, const float2*
                          const float4* fscale, int64_t n_modes, int64_t mode_stride,
                          int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                          int n_lags, int max_lag, float* acc, int acc_pitch, bool assign,
-                         int hist, int waves, size_t lds, hipStream_t s) {
+                         int hist, int waves, size_t lds, unsigned long long* work,
+                         float* comp, hipStream_t s) {
 #define NFS_PAIR_P(PP, NWW)                                                                 \
   return pair_launch<K, PP, NWW, KAHAN>(ring, spec, refspec, fscale, n_modes, mode_stride, \
                                         capacity, T0, T1, lags, n_lags, max_lag, acc,       \
-                                        acc_pitch, assign, hist, waves, lds, s)
+                                        acc_pitch, assign, hist, waves, lds, work, comp, s)
   if (waves <= 8) {
     switch (per_wave) {
       case 1: NFS_PAIR_P(1, 8);
@@ -546,7 +587,7 @@ hipError_t launch_pairs(const void* ring, int spec, bool kahan, const float2* re
                         int64_t capacity, int64_t T0, int64_t T1, const int32_t* lags,
                         int n_lags, int max_lag, float* acc, int acc_pitch, bool assign,
                         int modes, int hist, int waves, int per_wave, size_t lds,
-                        hipStream_t s) {
+                        unsigned long long* work, float* comp, hipStream_t s) {
   const char* r = static_cast<const char*>(ring);
   if (modes == 0) {  // the global-memory kernel (long delays)
     if (n_lags < 1 || n_lags > kGlobalLags) return hipErrorInvalidValue;
@@ -554,17 +595,17 @@ hipError_t launch_pairs(const void* ring, int spec, bool kahan, const float2* re
     if (kahan)
       hipLaunchKernelGGL(pair_global_kernel<true>, grid, dim3(256), 0, s, r, spec, refspec,
                          fscale, n_modes, mode_stride, capacity, T0, T1, lags, n_lags, acc,
-                         acc_pitch, assign);
+                         acc_pitch, assign, work, comp);
     else
       hipLaunchKernelGGL(pair_global_kernel<false>, grid, dim3(256), 0, s, r, spec, refspec,
                          fscale, n_modes, mode_stride, capacity, T0, T1, lags, n_lags, acc,
-                         acc_pitch, assign);
+                         acc_pitch, assign, work, comp);
     return hipGetLastError();
   }
 #define NFS_PAIR_CASE(KK, KH)                                                              \
   return pair_dispatch<KK, KH>(per_wave, r, spec, refspec, fscale, n_modes, mode_stride,  \
                                capacity, T0, T1, lags, n_lags, max_lag, acc, acc_pitch,   \
-                               assign, hist, waves, lds, s)
+                               assign, hist, waves, lds, work, comp, s)
   if (modes == 16) {
     if (kahan) NFS_PAIR_CASE(16, true);
     NFS_PAIR_CASE(16, false);

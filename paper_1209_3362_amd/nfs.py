@@ -87,6 +87,8 @@ def load_library():
         "nfs_power_spectra_2d": (i32, [P, P]),
         "nfs_backward": (i32, [P, P, P, P, P]),
         "nfs_probe_bandwidth": (i32, [i32, P, P, sz, P]),
+        "nfs_work_counters": (i32, [P, P]),
+        "nfs_set_pair_shapes": (i32, [P, P, i32]),
         "nfs_structure_function_noalloc": (i32, [ctypes.POINTER(NfsDesc), P, i64, P, P, P, P,
                                                  P]),
         "nfs_batch_workspace_size": (i32, [ctypes.POINTER(NfsDesc), i32, ctypes.POINTER(sz),
@@ -206,6 +208,7 @@ class Plan:
             else torch.device(device)
         self.n, self.lags, self.n_bins = int(n), [int(t) for t in lags], int(n_bins)
         self.in_dtype = in_dtype
+        self.spec, self.accum = spec, accum
         self.torch_dtype = torch.uint16 if in_dtype == "u16" else torch.float32
         self.window = None
         wptr = None
@@ -274,15 +277,42 @@ class Plan:
         self.stream.synchronize()
         self._borrowed.clear()
 
-    def tune_pairs(self):
-        """nfs_tune_pairs: time every pair-kernel launch shape on the frames
-        pushed so far and keep the fastest; returns [(modes, waves)] per lag
-        group. Synchronises the plan's stream."""
+    def tune_pairs(self, cache=True):
+        """Pair-kernel launch shapes per lag group, [(modes, waves)]: taken
+        from the tuning cache (tune_cache.py; key: GPU architecture, n, lags,
+        storage, accumulation) through nfs_set_pair_shapes when it holds this
+        plan's key, else timed by nfs_tune_pairs on the frames pushed so far
+        (synchronises the plan's stream) and stored in the cache."""
+        from . import tune_cache
+        path = tune_cache.cache_path() if cache else None
+        key = None
+        if path is not None:
+            arch = torch.cuda.get_device_properties(self.device).gcnArchName
+            key = tune_cache.cache_key(arch, self.n, self.lags, self.spec, self.accum)
+            shapes = None if tune_cache.refresh() else tune_cache.lookup(path, key)
+            if shapes is not None and self.set_pair_shapes(shapes, strict=False):
+                self.tuned_from_cache = True
+                return shapes
         n = ctypes.c_int32(0)
         self._check(self.lib.nfs_tune_pairs(self.handle, None, ctypes.byref(n)))
         arr = (ctypes.c_int32 * (2 * n.value))()
         self._check(self.lib.nfs_tune_pairs(self.handle, arr, ctypes.byref(n)))
-        return [(arr[2 * i], arr[2 * i + 1]) for i in range(n.value)]
+        shapes = [(arr[2 * i], arr[2 * i + 1]) for i in range(n.value)]
+        self.tuned_from_cache = False
+        if key is not None:
+            tune_cache.store(path, key, shapes)
+        return shapes
+
+    def set_pair_shapes(self, shapes, strict=True):
+        """nfs_set_pair_shapes: apply [(modes, waves)] per lag group. With
+        strict=False a rejected list returns False instead of raising."""
+        flat = [int(v) for pair in shapes for v in pair]
+        arr = (ctypes.c_int32 * max(1, len(flat)))(*flat)
+        st = self.lib.nfs_set_pair_shapes(self.handle, arr, ctypes.c_int32(len(shapes)))
+        if st != NFS_OK and not strict:
+            return False
+        self._check(st)
+        return True
 
     def accumulate(self):
         """Sum the pairs of every frame pushed so far (enqueued)."""
@@ -305,6 +335,17 @@ class Plan:
         if sync:
             self.synchronize()
         return D, counts, pairs, status
+
+    def work_counters(self, sync=True):
+        """nfs_work_counters: (frames transformed, frame pairs summed) as a
+        device int64 [2] tensor (synchronised and returned as two ints by
+        default)."""
+        out = torch.empty(2, dtype=torch.int64, device=self.device)
+        self._check(self.lib.nfs_work_counters(self.handle, _ptr(out)))
+        if not sync:
+            return out
+        self.stream.synchronize()
+        return int(out[0].item()), int(out[1].item())
 
     def power_spectra(self, sync=True):
         """P_tau(k) as float32 [n_lags][n][n/2 + 1] (nfs_power_spectra_2d):
@@ -521,19 +562,35 @@ class Batch:
         reuse of the frames' or outputs' memory) after the batch's run."""
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
 
-    def tune(self, frames_list):
-        """Tune every sequence's pair-kernel launch shape on its frames
-        (push, nfs_tune_pairs, reset per plan); returns the shapes."""
+    def tune(self, frames_list, cache=True):
+        """Every sequence's pair-kernel launch shapes: from the tuning cache
+        (tune_cache.py) when it holds the sequence's key, else timed on its
+        frames (push, nfs_tune_pairs, reset per plan) and cached; returns the
+        shapes."""
+        from . import tune_cache
         self._arrays(frames_list)  # validates shapes and types
         # The plans' pushes run on the batch's worker streams: let the
         # frames be complete first.
         torch.cuda.current_stream(self.device).synchronize()
+        path = tune_cache.cache_path() if cache else None
+        arch = torch.cuda.get_device_properties(self.device).gcnArchName
         shapes = []
         for j, f in enumerate(frames_list):
+            q = self.seqs[j]
+            key = tune_cache.cache_key(arch, q["n"], q["lags"], q.get("spec", "f32"),
+                                       q.get("accum", "plain"))
             p = ctypes.c_void_p()
             st = self.lib.nfs_batch_plan(self.handle, j, ctypes.byref(p))
-            if st == NFS_OK:
-                st = self.lib.nfs_push_frames(p, _ptr(f), ctypes.c_int64(f.shape[0]))
+            if st != NFS_OK:
+                raise NfsError(st, self.lib.nfs_status_string(st).decode())
+            cached = None if tune_cache.refresh() else tune_cache.lookup(path, key)
+            if cached is not None:
+                flat = [int(v) for pair in cached for v in pair]
+                arr = (ctypes.c_int32 * max(1, len(flat)))(*flat)
+                if self.lib.nfs_set_pair_shapes(p, arr, ctypes.c_int32(len(cached))) == NFS_OK:
+                    shapes.append(cached)
+                    continue
+            st = self.lib.nfs_push_frames(p, _ptr(f), ctypes.c_int64(f.shape[0]))
             n = ctypes.c_int32(0)
             arr = (ctypes.c_int32 * 64)()
             if st == NFS_OK:
@@ -542,7 +599,9 @@ class Batch:
                 st = self.lib.nfs_reset(p)
             if st != NFS_OK:
                 raise NfsError(st, self.lib.nfs_last_error(p).decode())
-            shapes.append([(arr[2 * i], arr[2 * i + 1]) for i in range(n.value)])
+            found = [(arr[2 * i], arr[2 * i + 1]) for i in range(n.value)]
+            tune_cache.store(path, key, found)
+            shapes.append(found)
         return shapes
 
     def run(self, frames_list, sync=True):

@@ -363,3 +363,63 @@ def test_tuned_pair_shapes_keep_parity():
         plan.tune_pairs()
     assert e.value.status == 7
     plan.close()
+
+
+@pytest.mark.parametrize("n,N,lags,capacity,chunk", [
+    (128, 64, [1, 2, 4, 8, 16], 64, None),             # one window
+    (64, 90, [0, 1, 3, 7, 30, 89, 90, 95], 100, 13),   # lag 0, lags without pairs
+    (32, 300, list(range(1, 40)), 60, 17),            # ring of 60: many windows
+    (16, 3000, [1, 2, 2401, 2600], 2700, 500),        # global-memory kernel
+])
+def test_work_counters(n, N, lags, capacity, chunk):
+    """The library's work counters: frames transformed = N, and the (t, tau)
+    pairs the pair kernels summed = sum over lags of max(0, N - tau), each
+    counted by the kernels from their own loop decisions."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfg = gen.config("c1", n=n, N=N, n_bins=n // 2)
+    say(f"work counters: {N} frames {n}x{n}, lags {lags[:6]}..., ring {capacity}, chunk {chunk}")
+    f = gen.make_stack(cfg, 14).cuda()
+    plan = nfs.Plan(n, lags, n // 2, in_dtype="f32", capacity=capacity)
+    for i in range(0, N, chunk or N):
+        plan.push(f[i:i + (chunk or N)])
+    plan.structure_function()
+    frames, pairs = plan.work_counters()
+    assert frames == N
+    assert pairs == sum(max(0, N - t) for t in lags)
+    plan.reset()
+    assert plan.work_counters() == (0, 0)
+    plan.close()
+
+
+def test_tuning_cache_and_set_pair_shapes(tmp_path, monkeypatch):
+    """The autotuner's choices persist in the JSON cache: a second plan with
+    the same key takes them without timing and gives the same D bit for bit;
+    nfs_set_pair_shapes refuses shapes the kernel does not support."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    monkeypatch.setenv("NFS_TUNE_CACHE", str(tmp_path / "shapes.json"))
+    monkeypatch.delenv("NFS_TUNE_REFRESH", raising=False)
+    cfg = gen.config("c2", n=64, N=120, n_bins=32)
+    lags = list(range(1, 30)) + [40, 60, 2500]  # two LDS groups? no: one, plus a global one
+    say("tuning cache: 120 frames 64x64 u16 (pushed twice over a 2600-slot ring), 32 lags")
+    f = gen.make_stack(cfg, 16).cuda()
+    out = []
+    for k in range(2):
+        plan = nfs.Plan(64, lags, 32, in_dtype="u16", capacity=2600)
+        plan.push(f)
+        shapes = plan.tune_pairs()
+        assert plan.tuned_from_cache == (k == 1)
+        plan.reset()
+        plan.push(f)
+        D, _, _, _ = plan.structure_function()
+        out.append((shapes, D.cpu().numpy()))
+        if k == 1:
+            with pytest.raises(nfs.NfsError):
+                plan.set_pair_shapes([(16, 99)] + shapes[1:])
+            with pytest.raises(nfs.NfsError):
+                plan.set_pair_shapes(shapes[:-1])
+            assert shapes[-1] == (0, 0)  # the long delay's group
+        plan.close()
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1], equal_nan=True)

@@ -135,6 +135,29 @@ def test_kahan_long_sum_of_equal_terms():
     assert ek <= ep
 
 
+def test_kahan_long_sum_across_many_windows():
+    """The one-cosine stack of 4000 frames through a 16-slot ring (about 360
+    pair windows, pushes of 7 frames): window totals are added with Kahan
+    compensation kept across windows, so the compensated sum stays at the
+    transform's precision while the plain one drifts."""
+    n, N = 16, 4000
+    modes = [(3, 2, 0.05, 0.7)]
+    say("kahan long sum, 16-slot ring: 4000 frames 16x16 cosine, lags 1, 5, pushes of 7")
+    f = gen.cosine_stack(n, N, modes, dtype=np.float32)
+    lags = [1, 5]
+    bidx = oracle.bin_index(n, 8)
+    b0 = bidx[3, 2]
+    C0 = oracle.bin_counts(bidx, 8)[b0]
+    want = np.array([(0.05 * n * n) ** 2 * (1 - np.cos(0.7 * t)) / C0 for t in lags])
+    Dp, _, _, _ = run_plan(f, lags, 8, "f32", capacity=16, chunk=7)
+    Dk, _, _, _ = run_plan(f, lags, 8, "f32", capacity=16, chunk=7, accum="kahan")
+    ep = np.abs(Dp[:, b0] / want - 1).max()
+    ek = np.abs(Dk[:, b0] / want - 1).max()
+    print(f"long sum over many windows: plain relative error {ep:.2e}, kahan {ek:.2e}")
+    assert ek < 1e-5
+    assert ek <= ep
+
+
 def test_kahan_across_ring_windows():
     """Kahan sums over several pair windows (ring smaller than the stack,
     uneven pushes) against the exact definition."""
