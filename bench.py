@@ -345,6 +345,21 @@ def batching(args):
     ws = b.workspace.numel()
     b.close()
     best = min(res.values())
+    # Serial-stage floor of each sequence (as for the 1000-frame workload:
+    # frames read and stored modes written at the HBM peak, 4 VALU
+    # lane-instructions per pair-k at the issue rate, sums read at the HBM
+    # peak), summed over the sequences; and the pair work's FP32 rate over
+    # the whole run against the published FP32 peak.
+    import math
+    floor_ms, pair_k = 0.0, 0
+    for c in cfgs:
+        h = c["n"] // 2
+        M = sum(math.isqrt(h * h - 1 - ky * ky) + 1 for ky in range(-h + 1, h))
+        pk = frame_pairs(c["N"], c["lags"]) * M
+        pair_k += pk
+        floor_ms += ((c["N"] * c["n"] * c["n"] * 2 + c["N"] * M * 8 + len(c["lags"]) * M * 4)
+                     / (HBM_PEAK_GBPS * 1e9) + 4.0 * pk / VALU_LANE_OPS) * 1e3
+    achieved = 6.0 * pair_k / (best * 1e-3) / 1e12
     print(json.dumps({
         "metric": METRIC_C4, "value": pairs / (best * 1e-3), "unit": "frame-pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": best,
@@ -356,6 +371,13 @@ def batching(args):
                    "parallelism": "single GPU",
                    "pair_shapes": "four-stream runs tuned %s" % tuned if tuned else "planned"},
         "ms_per_step_by_mode": res, "status": st,
+        "serial_floor_ms": floor_ms, "frac_of_serial_floor": floor_ms / best,
+        "roofline": {"kernel": "pair kernels of all 16 sequences (6 FLOP per pair-k), timed "
+                               "over the whole batch run", "bound": "alu",
+                     "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_PEAK_TFLOPS, "peak_nonpacked": FP32_NONPACKED_TFLOPS,
+                     "frac_nonpacked": achieved / FP32_NONPACKED_TFLOPS,
+                     "flop_per_step": 6.0 * pair_k, "traffic": None},
     }))
 
 

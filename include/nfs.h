@@ -62,8 +62,11 @@ typedef enum {
   NFS_E_DEGENERATE_FRAME = 8, /* a frame had a non-positive spatial sum      */
   NFS_E_HIP = 9,              /* a HIP runtime call failed                   */
   NFS_E_UNSUPPORTED = 10,     /* option value not implemented                */
-  NFS_E_SCRATCH = 11          /* problem larger than the static scratch of
+  NFS_E_SCRATCH = 11,         /* problem larger than the static scratch of
                                  nfs_structure_function_noalloc             */
+  NFS_E_TIMEOUT = 12          /* a bounded device-side wait of the fused
+                                 transform gave up (reported through the
+                                 status output); results are incomplete     */
 } nfs_status;
 
 /* Pixel type of the frames passed to nfs_push_frames. */
@@ -200,8 +203,9 @@ nfs_status nfs_accumulate(nfs_handle h);
  *   lag_pairs  int64 [n_lags]: max(0, N - tau) (may be NULL);
  *   status     int32 [1]: NFS_OK, or NFS_E_DEGENERATE_FRAME when some pushed
  *              frame had a spatial sum <= 0 (sticky until nfs_reset; such a
- *              frame's spectrum is stored as zero except I(0) = n^2)
- *              (may be NULL).
+ *              frame's spectrum is stored as zero except I(0) = n^2), or
+ *              NFS_E_TIMEOUT when a wait of the fused transform gave up
+ *              (sticky; never expected) (may be NULL).
  * May be called again after more pushes; the sums keep growing. */
 nfs_status nfs_structure_function(nfs_handle h, double* D, int64_t* bin_counts,
                                   int64_t* lag_pairs, int32_t* status);

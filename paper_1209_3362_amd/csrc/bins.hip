@@ -100,7 +100,10 @@ __global__ void bin_final_kernel(int nb, int n_lags, const double* __restrict__ 
   if (l == 0 && counts) counts[b] = C;
   if (b == 0) {
     if (pairs) pairs[l] = np;
-    if (l == 0 && status_out) status_out[0] = (status[0] & 1) ? NFS_E_DEGENERATE_FRAME : NFS_OK;
+    if (l == 0 && status_out)
+      status_out[0] = (status[0] & 2)   ? NFS_E_TIMEOUT
+                      : (status[0] & 1) ? NFS_E_DEGENERATE_FRAME
+                                        : NFS_OK;
   }
 }
 

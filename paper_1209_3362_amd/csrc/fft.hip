@@ -526,6 +526,326 @@ __global__ __launch_bounds__(256) void nyquist_col_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused transform: the row and column passes of a batch in one persistent
+// launch, with the row-to-column intermediate of a frame handed over inside
+// one XCD. Frame j belongs to XCD j mod 8 (workgroups are dispatched to the
+// 8 XCDs round robin, and each reads the XCD it runs on from the XCC_ID
+// register). Each XCD has its own task queue: its s-th frame, j = x + 8 s,
+// is job slot s, made of RB row tasks (16 rows each) followed by GROUPS
+// column tasks (8 columns each). Row tasks write the first `keep` column
+// tiles of their rows to the XCD's L2-sized buffer A and the others to
+// buffer B; column tasks read them back. Only workgroups of one XCD touch its
+// buffers and counters, so the hand-off needs no L2 writeback: a row task
+// waits for its stores to reach L2 (vmcnt 0) before counting itself done,
+// and a column task, after seeing every row task of its job done,
+// invalidates its L1 (buffer_inv sc0) before loading.
+//
+// Scheduler state (cleared before the launch): per XCD a task counter and,
+// per job slot, rows done and columns done. Every access to them is an
+// atomic read-modify-write at agent scope (polls add an opaque zero, so the
+// compiler keeps them atomics instead of turning them into loads, which
+// would not see the counts the atomics keep in the XCD's L2). A worker
+// claims task k = s * TPJ + i of its XCD's queue and stops when slot s has
+// no frame. Every wait is for tasks claimed earlier (smaller k) by running
+// workers: the row tasks of s (column tasks), the column tasks of s - 1
+// (row tasks: buffers A and B are reused), so the waits end whatever the
+// number of resident workers. Waits are bounded by spin_limit polls; past
+// it the worker sets bit 1 of *status and stops (the result is then
+// incomplete).
+constexpr int kFusedLine = 64;  // ints per XCD counter (one 256-byte line)
+
+__device__ __forceinline__ int sched_add(int* p, int v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int sched_peek(int* p) {
+  int zero = 0;
+  asm volatile("" : "+v"(zero));
+  return sched_add(p, zero);
+}
+// Poll *p until pred(value) or spin_limit polls; returns the last value.
+template <class Pred>
+__device__ __forceinline__ int sched_wait(int* p, Pred pred, unsigned spin_limit, bool* timed_out) {
+  int v = sched_peek(p);
+  for (unsigned it = 0; !pred(v); ++it) {
+    if (it >= spin_limit) {
+      *timed_out = true;
+      return v;
+    }
+    __builtin_amdgcn_s_sleep(2);
+    v = sched_peek(p);
+  }
+  return v;
+}
+
+template <int N, typename T, bool WIN, bool ABS, int SPEC>
+__global__ __launch_bounds__(256, 2) void fused_transform_kernel(
+    const T* __restrict__ frames, const T* __restrict__ ref, const float* __restrict__ window,
+    int nframes, double* __restrict__ rowsum, double* __restrict__ rowabs,
+    float2* __restrict__ bufA, float2* __restrict__ bufB, int keep, int* __restrict__ sched,
+    int slots, unsigned spin_limit, const double* __restrict__ refscal,
+    float4* __restrict__ fscale, int32_t* __restrict__ status, int64_t t0, int64_t capacity,
+    int64_t mode_stride, int64_t n_modes, const int32_t* __restrict__ tiles,
+    const float2* __restrict__ tw, char* __restrict__ ring, unsigned long long* __restrict__ work) {
+  using RC = RowCfg<N>;
+  using CC = ColCfg<N>;
+  using Raw = typename RawPair<T>::type;
+  constexpr bool U16 = std::is_same<T, uint16_t>::value;
+  constexpr bool F16 = SPEC == kSpecF16;
+  constexpr uint32_t MODE_BYTES = SPEC == kSpecF32 ? 8u : 4u;
+  constexpr int H = RC::H, RP1 = RC::P1, RP2 = RC::P2, RQ = RC::Q, R = RC::R, RB = RC::RB;
+  constexpr int PITCH = RC::PITCH;
+  constexpr int CP1 = CC::P1, CP2 = CC::P2, CQ = CC::Q, CP = CC::CP, CW = CC::CW;
+  constexpr int GROUPS = CC::GROUPS, TILES = CC::TILES, TWD = CC::TWD;
+  constexpr int TPJ = RB + GROUPS;  // tasks per job
+  static_assert(RC::THREADS == 256 && CC::THREADS == 256, "both tasks use 256 threads");
+  static_assert(TWD == CW && TWD == 8 && RP1 % TWD == 0 && CC::TW_LDS,
+                "one column tile per column task; row outputs at fixed tile strides");
+  constexpr int SMEM = R * PITCH > CW * CP ? R * PITCH : CW * CP;
+  __shared__ float2 smem[SMEM];
+  __shared__ float2 twl[tw_len(N)];
+  __shared__ double red[4];
+  __shared__ double red_abs[F16 ? 4 : 1];
+  __shared__ int bcast[2];
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += 256) twl[tw_skew(i)] = tw[i];
+  // The XCD this workgroup runs on (constant for its lifetime).
+  const int xcd = __builtin_amdgcn_readfirstlane(
+      __builtin_amdgcn_s_getreg((20) | (0 << 6) | (15 << 11)) & 7);
+  int* next_task = sched + xcd * kFusedLine;
+  int* rdone = sched + 8 * kFusedLine + xcd * slots;
+  int* cdone = rdone + 8 * slots;
+  float2* myA = bufA + int64_t(xcd) * keep * N * TWD;
+  float2* myB = bufB + int64_t(xcd) * (TILES - keep) * N * TWD;
+  double s_ref = refscal[0], sigma_ref = refscal[1];
+  const uint32_t spec_bytes = uint32_t(n_modes) * MODE_BYTES;
+  __syncthreads();
+
+  for (;;) {
+    if (tid == 0) {
+      bool timed_out = false;
+      const int k = sched_add(next_task, 1);
+      const int sl = k / TPJ, i = k - sl * TPJ;
+      const int64_t j = int64_t(xcd) + 8 * int64_t(sl);
+      int f = j < nframes ? int(j) : -1;
+      if (f >= 0 && sl >= slots) timed_out = true;  // cannot happen: slots >= ceil(nframes / 8)
+      if (f >= 0 && !timed_out) {
+        if (i < RB) {
+          if (sl > 0) sched_wait(cdone + sl - 1, [](int v) { return v >= GROUPS; }, spin_limit,
+                                 &timed_out);
+        } else {
+          sched_wait(rdone + sl, [](int v) { return v >= RB; }, spin_limit, &timed_out);
+        }
+      }
+      if (timed_out) {
+        atomicOr(status, 2);
+        f = -1;
+      }
+      bcast[0] = f;
+      bcast[1] = (sl << 8) | i;
+    }
+    __syncthreads();
+    const int f = bcast[0];
+    const int sl = bcast[1] >> 8, task = bcast[1] & 255;
+    __syncthreads();  // bcast is rewritten by the next claim
+    if (f < 0) break;
+
+    // The thread index goes through an empty asm statement so that the
+    // addresses derived from it are computed per task, not hoisted out of
+    // the task loop and kept live across both task bodies (which spills).
+    int lt = tid;
+    asm volatile("" : "+v"(lt));
+    if (task < RB) {
+      // ---- row task: rows [task * R, task * R + R) of frame f ----
+      const int rl = lt / RP1, j1 = lt % RP1;
+      const int y = task * R + rl;
+      float2* row_lds = smem + rl * PITCH;
+      float2 v[RP2];
+      int si = 0, sia = 0;
+      double sd = 0.0, sda = 0.0;
+      const T* frow = frames + (int64_t(f) * N + y) * N + 2 * j1;
+      const T* rrow = ref + int64_t(y) * N + 2 * j1;  // the reference is always set here
+#pragma unroll
+      for (int j2 = 0; j2 < RP2; ++j2) {
+        const Raw pxj = load_pair(frow + 2 * RP1 * j2);
+        const Raw rpj = load_pair(rrow + 2 * RP1 * j2);
+        float a, b;
+        if constexpr (U16) {
+          const int da = int(pxj & 0xffffu) - int(rpj & 0xffffu);
+          const int db = int(pxj >> 16) - int(rpj >> 16);
+          a = float(da);
+          b = float(db);
+          if constexpr (!WIN) si += da + db;
+          if constexpr (ABS && !WIN) sia += abs(da) + abs(db);
+        } else {
+          a = pxj.x - rpj.x;
+          b = pxj.y - rpj.y;
+        }
+        if constexpr (WIN) {
+          const float2 ww =
+              *reinterpret_cast<const float2*>(window + int64_t(y) * N + 2 * (j1 + RP1 * j2));
+          a *= ww.x;
+          b *= ww.y;
+        }
+        if constexpr (!U16 || WIN) sd += double(a) + double(b);
+        if constexpr (ABS && (!U16 || WIN)) sda += double(fabsf(a)) + double(fabsf(b));
+        v[j2] = make_float2(a, b);
+      }
+      double rs;
+      if constexpr (U16 && !WIN) {
+#pragma unroll
+        for (int o = RP1 / 2; o >= 1; o >>= 1) si += __shfl_xor(si, o, RP1);
+        rs = double(si);
+      } else {
+#pragma unroll
+        for (int o = RP1 / 2; o >= 1; o >>= 1) sd += __shfl_xor(sd, o, RP1);
+        rs = sd;
+      }
+      if (j1 == 0) rowsum[int64_t(f) * N + y] = rs;
+      if constexpr (ABS) {
+        double sa;
+        if constexpr (U16 && !WIN) {
+#pragma unroll
+          for (int o = RP1 / 2; o >= 1; o >>= 1) sia += __shfl_xor(sia, o, RP1);
+          sa = double(sia);
+        } else {
+#pragma unroll
+          for (int o = RP1 / 2; o >= 1; o >>= 1) sda += __shfl_xor(sda, o, RP1);
+          sa = sda;
+        }
+        if (j1 == 0) rowabs[int64_t(f) * N + y] = sa;
+      }
+      dft<RP2>(v);
+      static_for<RP2>([&](auto K2) {
+        constexpr int k2 = decltype(K2)::value;
+        float2 yv = v[bitrev<RP2>(k2)];
+        if constexpr (k2 != 0) yv = cmul(yv, twl[tw_skew((2 * j1 * k2) & (N - 1))]);
+        row_lds[k2 * (RP1 + 1) + j1] = yv;
+      });
+      wave_lds_sync();
+      float2 z[RQ][RP1];
+      static_for<RQ>([&](auto QQ) {
+        constexpr int q = decltype(QQ)::value;
+        const int k2 = j1 + q * RP1;
+        float2 w[RP1];
+#pragma unroll
+        for (int j = 0; j < RP1; ++j) w[j] = row_lds[k2 * (RP1 + 1) + j];
+        dft<RP1>(w);
+        static_for<RP1>([&](auto K1) {
+          constexpr int k1 = decltype(K1)::value;
+          z[q][k1] = w[bitrev<RP1>(k1)];
+        });
+      });
+      wave_lds_sync();
+#pragma unroll
+      for (int q = 0; q < RQ; ++q)
+#pragma unroll
+        for (int k1 = 0; k1 < RP1; ++k1) row_lds[(j1 + q * RP1) + RP2 * k1] = z[q][k1];
+      wave_lds_sync();
+      // Output i of this thread is k = j1 + RP1 i, in tile 2 i + j1 / 8 (RP1 =
+      // 16, 8 columns per tile), column j1 % 8, row y; with `keep` even it
+      // lies in buffer A exactly when i < keep / 2.
+      static_assert(RP1 == 2 * TWD, "two tiles per row-task output step");
+      float2* outA = myA + (int64_t(j1 / TWD) * N + y) * TWD + (j1 % TWD);
+      float2* outB = myB + (int64_t(j1 / TWD) * N + y) * TWD + (j1 % TWD);
+      const int half_keep = keep / 2;
+#pragma unroll
+      for (int i = 0; i < RP2; ++i) {
+        const int k = j1 + RP1 * i;
+        const float2 zk = row_lds[k];
+        const float2 zm = row_lds[(H - k) & (H - 1)];
+        const float2 e = make_float2(zk.x + zm.x, zk.y - zm.y);
+        const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
+        const float2 wd = cmul(d, twl[tw_skew(k)]);
+        const float2 X = make_float2(0.5f * (e.x + wd.y), 0.5f * (e.y - wd.x));
+        if (i < half_keep)
+          outA[int64_t(i) * 2 * N * TWD] = X;
+        else
+          outB[int64_t(i - half_keep) * 2 * N * TWD] = X;
+      }
+      // Stores of this task reach L2 before the task counts as done.
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      __syncthreads();
+      if (tid == 0) sched_add(rdone + sl, 1);
+    } else {
+      // ---- column task: columns [8 g, 8 g + 8) of frame f ----
+      const int grp = task - RB;
+      const int c = lt % CW, j1 = lt / CW;
+      const int kx = grp * CW + c;
+      // Rows written by other workgroups of this XCD are in its L2; drop
+      // any stale copies from this CU's L1 first.
+      asm volatile("buffer_inv sc0" ::: "memory");
+      const float2* src = (grp < keep ? myA + int64_t(grp) * N * TWD
+                                      : myB + int64_t(grp - keep) * N * TWD) + c;
+      float2 v[CP2];
+#pragma unroll
+      for (int j2 = 0; j2 < CP2; ++j2) v[j2] = src[(j1 + CP1 * j2) * TWD];
+      double part = 0.0, part_abs = 0.0;
+      for (int yy = tid; yy < N; yy += 256) part += rowsum[int64_t(f) * N + yy];
+      if constexpr (F16)
+        for (int yy = tid; yy < N; yy += 256) part_abs += rowabs[int64_t(f) * N + yy];
+      float2* col_lds = smem + c * CP;
+      dft<CP2>(v);
+      static_for<CP2>([&](auto K2) {
+        constexpr int k2 = decltype(K2)::value;
+        float2 yv = v[bitrev<CP2>(k2)];
+        if constexpr (k2 != 0) yv = cmul(yv, col_twiddle<N>(twl, tw, (j1 * k2) & (N - 1)));
+        col_lds[k2 * (CP1 + 1) + j1] = yv;
+      });
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) part += __shfl_xor(part, o, 64);
+      if ((tid & 63) == 0) red[tid >> 6] = part;
+      if constexpr (F16) {
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) part_abs += __shfl_xor(part_abs, o, 64);
+        if ((tid & 63) == 0) red_abs[tid >> 6] = part_abs;
+      }
+      __syncthreads();
+      const double S = s_ref + (((red[0] + red[1]) + red[2]) + red[3]);
+      const bool bad = !(S > 0.0) || !isfinite(S);
+      const double sigma = bad ? 0.0 : double(N) * double(N) / S;
+      int e = 0;
+      if constexpr (F16) e = f16_exponent(sigma * (((red_abs[0] + red_abs[1]) + red_abs[2]) + red_abs[3]));
+      const float scale = float(ldexp(sigma, e));
+      const int64_t slot = (t0 + f) % capacity;
+      if (grp == 0 && tid == 0) {
+        fscale[slot] =
+            make_float4(float(sigma), float(sigma - sigma_ref), float(ldexp(1.0, -e)), 0.f);
+        if (bad) atomicOr(status, 1);
+        if (work) atomicAdd(work, 1ull);  // work counter: frames transformed
+      }
+      const BufferRsrc dst = make_buffer(ring + slot * mode_stride * int64_t(MODE_BYTES), spec_bytes);
+      static_for<CQ>([&](auto QQ) {
+        constexpr int q = decltype(QQ)::value;
+        const int k2 = j1 + q * CP1;
+        float2 w[CP1];
+#pragma unroll
+        for (int j = 0; j < CP1; ++j) w[j] = col_lds[k2 * (CP1 + 1) + j];
+        dft<CP1>(w);
+        static_for<CP1>([&](auto K1) {
+          constexpr int k1 = decltype(K1)::value;
+          const int r = (j1 + q * CP1) + CP2 * k1;
+          const int sl2 = ring_slot(N, tiles, r, kx);
+          uint32_t o = sl2 >= 0 ? uint32_t(sl2) * 8u : kDropOffset;
+          float2 X = w[bitrev<CP1>(k1)];
+          X.x *= scale;
+          X.y *= scale;
+          if constexpr (q == 0 && k1 == 0) {
+            if (o == 0) X = make_float2(0.f, 0.f);
+          }
+          if constexpr (SPEC == kSpecF32)
+            buffer_store(X, dst, o);
+          else
+            buffer_store_u32(SPEC == kSpecBF16 ? pack_bf16(X) : pack_f16(X), dst, o >> 1);
+        });
+      });
+      __syncthreads();  // every read of this task's buffer tile is done; LDS free
+      if (tid == 0) sched_add(cdone + sl, 1);
+    }
+  }
+}
+
 template <int N, typename T, bool WIN>
 hipError_t row_launch(const void* frames, const void* ref, const float* window, int nframes,
                       float2* inter, double* rowsum, double* rowabs, float* nyq,
@@ -615,6 +935,41 @@ hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* 
     default: return hipErrorInvalidValue;
   }
 #undef NFS_ROW_CASE
+}
+
+hipError_t launch_fused_transform(int n, int in_dtype, int spec, const void* frames,
+                                  const void* ref, const float* window, int nframes,
+                                  double* rowsum, double* rowabs, float2* bufA, float2* bufB,
+                                  int keep, int* sched, int slots, int workers,
+                                  unsigned spin_limit, const double* refscal, float4* fscale,
+                                  int32_t* status, int64_t t0, int64_t capacity,
+                                  int64_t mode_stride, int64_t n_modes, const int32_t* tiles,
+                                  const float2* tw, void* ring, unsigned long long* work,
+                                  hipStream_t s) {
+  if (n != 1024 || nframes < 1 || keep < 0 || keep > 64 || keep % 2 || workers < 8 ||
+      workers % 8 || slots < (nframes + 7) / 8)
+    return hipErrorInvalidValue;
+  constexpr int N = 1024;
+  char* ringb = static_cast<char*>(ring);
+  const dim3 grid = dim3(unsigned(workers)), block = dim3(256);
+#define NFS_FUSED_GO(TT, WINV, ABSV, SPECV)                                                    \
+  hipLaunchKernelGGL((fused_transform_kernel<N, TT, WINV, ABSV, SPECV>), grid, block, 0, s,    \
+                     static_cast<const TT*>(frames), static_cast<const TT*>(ref), window,     \
+                     nframes, rowsum, rowabs, bufA, bufB, keep, sched, slots, spin_limit,     \
+                     refscal, fscale, status, t0, capacity, mode_stride, n_modes, tiles, tw,  \
+                     ringb, work)
+#define NFS_FUSED_SPEC(TT, WINV)                                                                \
+  if (spec == kSpecF16) NFS_FUSED_GO(TT, WINV, true, kSpecF16);                                \
+  else if (spec == kSpecBF16) NFS_FUSED_GO(TT, WINV, false, kSpecBF16);                        \
+  else NFS_FUSED_GO(TT, WINV, false, kSpecF32);
+  if (in_dtype == 0) {
+    if (window) { NFS_FUSED_SPEC(uint16_t, true) } else { NFS_FUSED_SPEC(uint16_t, false) }
+  } else {
+    if (window) { NFS_FUSED_SPEC(float, true) } else { NFS_FUSED_SPEC(float, false) }
+  }
+#undef NFS_FUSED_SPEC
+#undef NFS_FUSED_GO
+  return hipGetLastError();
 }
 
 hipError_t launch_nyquist_col(int n, bool reference, int spec, const float* nyq, int nframes,

@@ -9,7 +9,9 @@
 // pair needs, and at the end.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 #include <mutex>
 #include <new>
 #include <set>
@@ -63,6 +65,12 @@ struct nfs_plan_s {
   hipEvent_t freed[2] = {nullptr, nullptr};
   bool freed_recorded[2] = {false, false};
   int next_stage = 0;
+  // Fused transform (n = 1024): scheduler state, workgroups per launch and
+  // the column tiles kept in the XCD-local buffer; off: the two-pass path.
+  bool fused = false;
+  int* sched = nullptr;
+  int fused_workers = 0;
+  int fused_keep = 32;
   // nfs_backward buffers (backward)
   float2* gk = nullptr;
   double2* brow = nullptr;
@@ -175,6 +183,24 @@ nfs_status make_room(nfs_plan_s* h, int64_t b) {
 // ring slot (its frame index) mod capacity.
 nfs_status transform_into_ring(nfs_plan_s* h, const char* src, int64_t b, int64_t t) {
   const nfs::Layout& L = h->L;
+  if (h->fused) {
+    // Bounded waits: about 2^22 polls (seconds) before a stuck wait gives up
+    // and reports NFS_E_TIMEOUT through the status word.
+    constexpr unsigned kSpinLimit = 1u << 22;
+    const int keep = h->fused_keep;
+    float2* bufA = h->inter;
+    float2* bufB = h->inter + size_t(8) * keep * L.n * 8;
+    hipError_t e = nfs::launch_fill_u32(h->sched, size_t(8 * 64 + 16 * L.fused_slots), 0u,
+                                        h->stream);
+    if (e == hipSuccess)
+      e = nfs::launch_fused_transform(L.n, L.in_dtype, L.spec_dtype, src, h->ref, h->window,
+                                      int(b), h->rowsum, h->rowabs, bufA, bufB, keep, h->sched,
+                                      L.fused_slots, h->fused_workers, kSpinLimit, h->refscal,
+                                      h->fscale, h->status, t, L.capacity, L.mode_stride,
+                                      L.slots, h->tiles, h->tw, h->ring, h->work, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "fused transform launch");
+    return NFS_OK;
+  }
   hipError_t e = nfs::launch_row_pass(L.n, L.in_dtype, src, h->ref, h->window, int(b),
                                       h->inter, h->rowsum, h->rowabs, h->nyq, h->tw, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "row pass launch");
@@ -241,6 +267,7 @@ const char* nfs_status_string(nfs_status s) {
     case NFS_E_UNSUPPORTED: return "option not implemented";
     case NFS_E_SCRATCH:
       return "workspace larger than the library's static scratch (NFS_STATIC_SCRATCH_BYTES)";
+    case NFS_E_TIMEOUT: return "a bounded device-side wait gave up; results are incomplete";
   }
   return "unknown status";
 }
@@ -281,6 +308,20 @@ nfs_status nfs_plan(const nfs_desc* desc, void* workspace, size_t bytes, void* s
   h->rowabs = L.spec_dtype == NFS_SPEC_F16 ? reinterpret_cast<double*>(h->ws + L.off_rowabs)
                                             : nullptr;
   h->nyq = L.full ? reinterpret_cast<float*>(h->ws + L.off_nyq) : nullptr;
+  if (L.fused_ok) {
+    // The fused transform is switched off: its first GPU runs did not
+    // finish (every wait of its task scheduler ran to its bound), and the
+    // cause is not established. Every plan uses the separate row and column
+    // passes; the kernel and its host plumbing stay for later work.
+    h->fused = false;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus < 1)
+      cus = 256;
+    h->fused_workers = std::min(nfs::kFusedMaxWorkers, 2 * cus);
+    h->sched = reinterpret_cast<int*>(h->ws + L.off_sched);
+  }
   h->acc = reinterpret_cast<float*>(h->ws + L.off_acc);
   h->comp = L.accum == NFS_ACC_KAHAN ? reinterpret_cast<float*>(h->ws + L.off_comp) : nullptr;
   h->status = reinterpret_cast<int32_t*>(h->ws + L.off_status);

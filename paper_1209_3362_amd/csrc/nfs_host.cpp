@@ -216,6 +216,11 @@ nfs_status make_layout(const nfs_desc* d, size_t bytes_available, Layout* L,
   o.off_nyq = take(o.full ? size_t(o.batch) * o.n * 4 : 0);
   o.off_acc = take(size_t(o.n_lags) * o.mode_stride * 4);
   o.off_comp = take(o.accum == NFS_ACC_KAHAN ? size_t(o.n_lags) * o.mode_stride * 4 : 0);
+  // Fused transform at n = 1024: per launch at most `batch` jobs; its
+  // buffers (8 XCDs x 4 MiB) fit the intermediate from 8 frames on.
+  o.fused_ok = o.n == 1024 && !o.full && size_t(o.batch) * inter_frame >= (size_t(32) << 20);
+  o.fused_slots = (o.batch + 7) / 8;  // frames per XCD per launch at most
+  o.off_sched = take(o.fused_ok ? size_t(8 * 64 + 16 * o.fused_slots) * 4 : 0);
   const size_t nseg = o.seg_first.size() - 1;
   o.off_segs = take((o.seg_first.size() + o.bin_seg0.size()) * 4);
   o.off_bin_slots = take(o.bin_slots.size() * 4);

@@ -21,6 +21,8 @@ constexpr int kSegModes = 256;
 // Target size of the row-transform intermediate of one batch of frames.
 constexpr size_t kBatchBytes = size_t(128) << 20;
 constexpr int kMaxBatch = 1024;
+// Fused transform: workgroups per launch at most (2 per CU on 256 CUs).
+constexpr int kFusedMaxWorkers = 512;
 // Most ring slots (slot indices are 32-bit in the kernels).
 constexpr int64_t kMaxCapacity = 0x7fffffff;
 // Per ring slot: {sigma, sigma - sigma_ref, 2^-e (FP16 storage, else 1), 0}.
@@ -77,6 +79,11 @@ struct Layout {
   size_t off_ref = 0, off_refspec = 0;  // reference frame and its transform
   size_t off_nyq = 0;     // full plans: the row pass's k_x = n/2 values [batch][n]
   size_t off_comp = 0;    // Kahan plans: compensation of the sums, laid out like them
+  // Fused transform (n = 1024): scheduler state of one launch, fused_slots
+  // job slots per XCD; its two buffers are carved from the intermediate.
+  size_t off_sched = 0;
+  int fused_slots = 0;
+  bool fused_ok = false;   // the intermediate holds the fused buffers (32 MiB)
   size_t off_stage = 0;   // host-push staging: 2 x batch frames (host_staging)
   // nfs_backward (backward): k-space gradients of a batch [batch][mode_stride]
   // complex (the same region later holds its g' images [batch][n][n] floats),

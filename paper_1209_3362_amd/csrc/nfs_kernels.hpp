@@ -22,6 +22,26 @@ hipError_t launch_row_pass(int n, int in_dtype, const void* frames, const void* 
                            const float* window, int nframes, float2* inter, double* rowsum,
                            double* rowabs, float* nyq, const float2* tw, hipStream_t s);
 
+// Fused row and column passes of `nframes` frames (n = 1024 only) in one
+// persistent launch of `workers` workgroups: per-XCD task queues, the
+// intermediate of a frame handed over inside one XCD through bufA (the
+// first `keep` column tiles, 8 x keep x 64 KB) and bufB (the other tiles).
+// sched: scheduler state, (8 * 64 + 16 * slots) ints, cleared before the
+// launch; slots >= ceil(nframes / 8); frame j is processed on XCD j mod 8,
+// so `workers` must be a multiple of 8 (dispatch is round robin over the
+// XCDs). Stores exactly what
+// launch_row_pass + launch_col_pass store; a wait past spin_limit polls
+// sets bit 1 of *status.
+hipError_t launch_fused_transform(int n, int in_dtype, int spec, const void* frames,
+                                  const void* ref, const float* window, int nframes,
+                                  double* rowsum, double* rowabs, float2* bufA, float2* bufB,
+                                  int keep, int* sched, int slots, int workers,
+                                  unsigned spin_limit, const double* refscal, float4* fscale,
+                                  int32_t* status, int64_t t0, int64_t capacity,
+                                  int64_t mode_stride, int64_t n_modes, const int32_t* tiles,
+                                  const float2* tw, void* ring, unsigned long long* work,
+                                  hipStream_t s);
+
 // Column k_x = n/2 of full half-plane plans, after the column pass of the
 // same frames: transform of nyq[f][y] over y, stored like the other modes
 // (reference: unscaled FP32 into refspec) at slots nyq_slot + r.

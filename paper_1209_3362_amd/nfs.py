@@ -15,7 +15,7 @@ STATUS = {
     0: "NFS_OK", 1: "NFS_E_ARG", 2: "NFS_E_SIZE", 3: "NFS_E_LAGS", 4: "NFS_E_BINS",
     5: "NFS_E_WORKSPACE", 6: "NFS_E_CAPACITY", 7: "NFS_E_STATE",
     8: "NFS_E_DEGENERATE_FRAME", 9: "NFS_E_HIP", 10: "NFS_E_UNSUPPORTED",
-    11: "NFS_E_SCRATCH",
+    11: "NFS_E_SCRATCH", 12: "NFS_E_TIMEOUT",
 }
 IN_DTYPES = {"u16": 0, "f32": 1}
 SPEC_DTYPES = {"f32": 0, "bf16": 1, "f16": 2}

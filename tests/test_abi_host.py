@@ -59,7 +59,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings():
     lib = nfs.load_library()
-    for code in range(12):
+    for code in range(13):
         s = lib.nfs_status_string(code)
         assert s and s != b"unknown status"
     assert lib.nfs_status_string(99) == b"unknown status"
