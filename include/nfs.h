@@ -332,7 +332,8 @@ const char* nfs_last_error(nfs_handle h);
  *   [0] frames transformed (one per pushed frame; a backward that
  *       recomputes spectra adds one per frame it transforms again);
  *   [1] (target, lag) frame pairs whose terms the pair kernels summed, as
- *       counted by those kernels from their own loop decisions; after
+ *       counted by each wave of those kernels from its own lag slice and
+ *       window bounds (the bounds of its masks); after
  *       nfs_structure_function this equals sum over the lags of
  *       max(0, N - tau) (the processing section's count of differences per
  *       delay), N the frames pushed.

@@ -255,9 +255,7 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
 #pragma unroll
   for (int s = 0; s < MAXLW; ++s)
     if (s < l_count) first_max = max(first_max, first[s]);
-  // Work counter: (target, lag) pairs this wave sums, counted from the same
-  // wave-uniform decisions that select the sums (scalar registers).
-  uint64_t npairs = 0;
+
 
   // Lane (m, g) reads rows r + g * RPT + i of column m for a ring row r.
   const float2* lane_hist = hist + g * RPT * K + m;
@@ -307,13 +305,11 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
       if (s < l_count) {
         if (full && c >= first[s]) {
           acc_plain(cur, o, s);
-          npairs += S;
         } else if (c + S > first[s]) {
           // Targets [lo, hi) of the chunk have partners. When both ends fall
           // on lane boundaries every lane's run is wholly in or out: plain
           // sums on the lanes that are in; otherwise per-target selects.
           const int lo = max(first[s] - c, 0), hi = min(len - c, S);
-          npairs += hi > lo ? uint64_t(hi - lo) : 0;
           if (lo % RPT == 0 && hi % RPT == 0) {
             if (g * RPT >= lo && g * RPT < hi) acc_plain(cur, o, s);
           } else {
@@ -395,27 +391,30 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(
   if (l_count == MAXLW && consecutive) {
     for (; c < lenS; c += S)
       chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LMax{}, Yes{}, cur, rows); });
-    npairs += uint64_t(MAXLW * S) * uint64_t((lenS - ca) / S);
   } else if (l_count == MAXLW) {
     for (; c < lenS; c += S)
       chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LMax{}, No{}, cur, rows); });
-    npairs += uint64_t(MAXLW * S) * uint64_t((lenS - ca) / S);
   } else if (MAXLW > 1 && l_count == LS && consecutive) {
     for (; c < lenS; c += S)
       chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LLess{}, Yes{}, cur, rows); });
-    npairs += uint64_t(LS * S) * uint64_t((lenS - ca) / S);
   } else if (MAXLW > 1 && l_count == LS) {
     for (; c < lenS; c += S)
       chunk(c, [&](int, const float2* cur, auto&& rows) { full_chunk(LLess{}, No{}, cur, rows); });
-    npairs += uint64_t(LS * S) * uint64_t((lenS - ca) / S);
   } else {
     // Waves without lags only copy rows.
     for (; c < lenS; c += S) chunk(c, [](int, const float2*, auto&&) {});
   }
   for (; c < len; c += S) chunk(c, generic);
 
-  if (work && blockIdx.x == 0 && lane == 0 && l_count > 0)
-    atomicAdd(work, static_cast<unsigned long long>(npairs));
+  // Work counter: the (target, lag) pairs this wave summed, from the same
+  // per-lag first partnered offsets and window length that bound its masks.
+  if (work && blockIdx.x == 0 && lane == 0 && l_count > 0) {
+    unsigned long long npairs = 0;
+#pragma unroll
+    for (int s = 0; s < MAXLW; ++s)
+      if (s < l_count && len > first[s]) npairs += static_cast<unsigned long long>(len - first[s]);
+    atomicAdd(work, npairs);
+  }
 
   // Lanes g = 0..G-1 of one mode hold partial sums over disjoint frames;
   // their total goes through LDS so the workgroup adds its K x n_lags block
@@ -503,7 +502,6 @@ __global__ __launch_bounds__(256) void pair_global_kernel(
 #pragma unroll
   for (int s = 0; s < GL; ++s) run[s] = cmp[s] = part[s] = 0.f;
   int64_t slot = T0 % capacity;
-  uint64_t npairs = 0;  // work counter: (target, lag) pairs summed
   for (int64_t t = T0; t < T1; ++t) {
     const float2 at = value(slot);
 #pragma unroll
@@ -513,7 +511,6 @@ __global__ __launch_bounds__(256) void pair_global_kernel(
         const float2 o = value(so);
         const float dx = at.x - o.x, dy = at.y - o.y;
         part[s] = fmaf(dx, dx, fmaf(dy, dy, part[s]));
-        ++npairs;
       }
     }
     if (KAHAN && ((t - T0) % 32 == 31 || t + 1 == T1)) {
@@ -528,7 +525,16 @@ __global__ __launch_bounds__(256) void pair_global_kernel(
     }
     if (++slot == capacity) slot = 0;
   }
-  if (work && m == 0) atomicAdd(work, static_cast<unsigned long long>(npairs));
+  // Work counter: the (target, lag) pairs summed, targets t in [T0, T1) with
+  // t >= tau (the bounds of the loop above).
+  if (work && m == 0) {
+    unsigned long long npairs = 0;
+    for (int s = 0; s < n_lags && s < GL; ++s) {
+      const int64_t from = T0 > tau[s] ? T0 : int64_t(tau[s]);
+      if (T1 > from) npairs += static_cast<unsigned long long>(T1 - from);
+    }
+    atomicAdd(work, npairs);
+  }
 #pragma unroll
   for (int s = 0; s < GL; ++s) {
     if (s < n_lags) {
