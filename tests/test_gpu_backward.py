@@ -31,14 +31,14 @@ def _check(name, got, want, tol=1e-4):
 
 
 def _run(frames, lags, n_bins, G, window, in_dtype="f32", spec="f32", chunk=None,
-         capacity=None):
+         capacity=None, full_spectra=False):
     import paper_1209_3362_amd as nfs
     N, n = frames.shape[0], frames.shape[-1]
     t = frames.to("cuda")
     w = None if window is None else torch.from_numpy(window.astype(np.float32)).cuda()
     cap = capacity or max(N, max(lags) + 1)
     plan = nfs.Plan(n, lags, n_bins, in_dtype=in_dtype, capacity=cap, window=w, spec=spec,
-                    backward=True)
+                    backward=True, full_spectra=full_spectra)
     if chunk:
         for i in range(0, N, chunk):
             plan.push(t[i:i + chunk])
@@ -179,6 +179,30 @@ def test_backward_recompute_matches_oracle(spec, tol):
     gf, gw = _run(f, lags, 64, G, w, spec=spec, chunk=7, capacity=20)
     _check("frames", gf, want["frames"], tol=tol)
     _check("window", gw, want["window"], tol=tol)
+
+
+@pytest.mark.parametrize("capacity", [None, 24])
+def test_backward_of_full_spectra_plans(capacity):
+    """A plan that stores the entire half plane (its extra modes lie in no
+    ring, so they carry no gradient) gives the gradient of the plan that
+    stores the ring modes only, resident and with the spectra recomputed
+    (a 24-slot ring for 60 frames, largest lag 9), and both match the
+    oracle adjoint."""
+    require_gpu()
+    cfg = gen.config("c1", n=64, N=60, n_bins=32)
+    lags = [1, 4, 9]
+    say(f"backward, full spectra: 60 frames 64x64 f32, Hann window, lags 1,4,9, ring {capacity}")
+    f = gen.make_stack(cfg, 47)
+    w = _hann(64) + 0.05
+    G = np.random.default_rng(47).standard_normal((3, 32))
+    want = oracle.structure_function_grad(f.numpy(), lags, 32, G, window=w)
+    got = {}
+    for full in (False, True):
+        got[full] = _run(f, lags, 32, G, w, chunk=17, capacity=capacity, full_spectra=full)
+        _check(f"frames (full={full})", got[full][0], want["frames"])
+        _check(f"window (full={full})", got[full][1], want["window"])
+    _check("frames, full vs ring-modes plan", got[True][0], got[False][0], tol=1e-6)
+    _check("window, full vs ring-modes plan", got[True][1], got[False][1], tol=1e-6)
 
 
 def test_backward_recompute_long_lags_u16():
