@@ -53,6 +53,31 @@ def test_batch_equals_single_plans():
             assert np.array_equal(x, y, equal_nan=True), c["name"]
 
 
+def test_batch_mixed_storage_and_accumulation_equals_single_plans():
+    """Sequences of one batch with different spectrum storage and sum
+    accumulation (FP32/BF16/FP16, plain/Kahan) each give exactly what a
+    single plan with the same options gives."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfgs = _small_batch(count=6, seed=11)
+    opts = [("f32", "plain"), ("bf16", "kahan"), ("f16", "plain"), ("f32", "kahan"),
+            ("bf16", "plain"), ("f16", "kahan")]
+    say("batch: 6 sequences with mixed storage/accumulation, 3 streams, seed 11")
+    frames = [gen.make_stack(c, c["seed"], device="cuda") for c in cfgs]
+    seqs = [dict(_seq(c), spec=sp, accum=ac) for c, (sp, ac) in zip(cfgs, opts)]
+    b = nfs.Batch(seqs, streams=3)
+    got = _np(b.run(frames))
+    b.close()
+    for c, f, g, (sp, ac) in zip(cfgs, frames, got, opts):
+        plan = nfs.Plan(c["n"], c["lags"], c["n_bins"], in_dtype="u16",
+                        capacity=max(c["N"], c["lags"][-1] + 1), spec=sp, accum=ac)
+        plan.push(f)
+        want = [x.cpu().numpy() for x in plan.structure_function()]
+        plan.close()
+        for x, y in zip(g, want):
+            assert np.array_equal(x, y, equal_nan=True), (c["name"], sp, ac)
+
+
 def test_batch_graph_replays():
     """Three replays with eager work and a change of the frame data between
     them; every replay equals an eager batch run on the data it read."""
