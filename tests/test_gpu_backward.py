@@ -205,6 +205,32 @@ def test_backward_of_full_spectra_plans(capacity):
     _check("window, full vs ring-modes plan", got[True][1], got[False][1], tol=1e-6)
 
 
+def test_backward_after_host_pushes():
+    """Frames pushed from pinned host memory through the staging buffers,
+    then the gradient (resident and recomputed): the same as after device
+    pushes, bit for bit."""
+    import paper_1209_3362_amd as nfs
+    require_gpu()
+    cfg = gen.config("c1", n=64, N=50, n_bins=32)
+    lags = [1, 3, 8]
+    say("backward after host pushes: 50 frames 64x64 f32, lags 1,3,8, rings 50 and 20")
+    f = gen.make_stack(cfg, 48)
+    G = torch.from_numpy(np.random.default_rng(48).standard_normal((3, 32)))
+    t = f.cuda()
+    for cap in (50, 20):
+        out = []
+        for host in (False, True):
+            plan = nfs.Plan(64, lags, 32, in_dtype="f32", capacity=cap, backward=True,
+                            host_staging=True)
+            for i in range(0, 50, 12):
+                part = f[i:i + 12]
+                plan.push(part.pin_memory() if host else part.cuda())
+            gf, gw = plan.backward(G, t)
+            out.append((gf.cpu().numpy(), gw.cpu().numpy()))
+            plan.close()
+        assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1]), cap
+
+
 def test_backward_recompute_long_lags_u16():
     """Recompute with a largest lag of 450 (the global-memory gradient
     kernel) over 1000 u16 frames in a 905-slot ring: windows of 5 targets."""

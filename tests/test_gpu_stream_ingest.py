@@ -13,10 +13,10 @@ from gpu_util import assert_D_close, require_gpu, say
 pytestmark = pytest.mark.gpu
 
 
-def _run(frames, lags, n_bins, in_dtype, capacity, chunks, host, pinned=True):
+def _run(frames, lags, n_bins, in_dtype, capacity, chunks, host, pinned=True, **opts):
     import paper_1209_3362_amd as nfs
     plan = nfs.Plan(frames.shape[-1], lags, n_bins, in_dtype=in_dtype, capacity=capacity,
-                    host_staging=True)
+                    host_staging=True, **opts)
     i = 0
     for k, c in enumerate(chunks):
         part = frames[i:i + c]
@@ -51,6 +51,25 @@ def test_host_push_equals_device_push_with_ring_wrap(host):
     exact = oracle.structure_function(f.numpy(), lags, 64)
     assert_D_close(got[0], exact["D"], rtol=1e-4)
     assert np.array_equal(got[1], exact["counts"])
+
+
+@pytest.mark.parametrize("spec,accum", [("bf16", "kahan"), ("f16", "plain")])
+def test_host_push_16bit_storage_windowed(spec, accum):
+    """Host pushes into plans with 16-bit spectra, Kahan sums and a window,
+    with ring wrap: the same bytes as device pushes."""
+    require_gpu()
+    cfg = gen.config("c1", n=64, N=70, n_bins=32)
+    lags = [1, 2, 5, 11, 23]
+    say(f"host ingest: 70 frames 64x64 f32, {spec}/{accum}, Hann window, capacity 40")
+    f = gen.make_stack(cfg, 23)
+    w = torch.from_numpy((np.outer(np.hanning(64), np.hanning(64)) + 0.1).astype(np.float32))
+    opts = dict(spec=spec, accum=accum, window=w.cuda())
+    chunks = [9, 17, 30, 14]
+    ref = _run(f, lags, 32, "f32", 40, chunks, host=False, **opts)
+    got = _run(f, lags, 32, "f32", 40, chunks, host=True, **opts)
+    for a, b in zip(ref[:3], got[:3]):
+        assert np.array_equal(a, b, equal_nan=True)
+    assert got[3] == ref[3] == 0
 
 
 def test_host_push_pageable_u16():
