@@ -88,7 +88,11 @@ enum { NFS_SPEC_F32 = 0, NFS_SPEC_BF16 = 1, NFS_SPEC_F16 = 2 };
 /* Per-mode pair accumulation.
  *   NFS_ACC_PLAIN: FP32 running sums;
  *   NFS_ACC_KAHAN: FP32 sums over each chunk of 32 target frames, added to
- *                  the running sum with Kahan compensation. */
+ *                  the running sum with Kahan compensation; when a ring
+ *                  holds fewer frames than were pushed, each window's totals
+ *                  are added to the stored sums with the compensation kept
+ *                  per (mode, delay) in the workspace, so it holds over the
+ *                  whole average. */
 enum { NFS_ACC_PLAIN = 0, NFS_ACC_KAHAN = 1 };
 
 typedef struct {
