@@ -361,7 +361,10 @@ __global__ __launch_bounds__(256) void finish_kernel(
   if (p >= px) return;
   const float w = WIN ? window[p] : 1.f;
   double acc = 0.0;
-#pragma unroll 4
+  // 16 frames' loads in flight per thread (4: 0.950 ms of backward on the
+  // 256 x 512^2 workload, 8: 0.935, 16: 0.928, 32: 1.03 at a lower
+  // occupancy).
+#pragma unroll 16
   for (int f = 0; f < nframes; ++f) {
     const double2 s = scal[f];
     const double du = (double(gprime[int64_t(f) * px + p]) - s.y) * s.x;
